@@ -1,0 +1,209 @@
+/*
+ * geer.h -- C ABI of the MI355X GEER library.
+ *
+ * GEER answers epsilon-approximate pairwise effective resistance queries
+ * (Yang & Tang, "Efficient Estimation of Pairwise Effective Resistance",
+ * Definition 2.2): given an undirected, unweighted, connected, non-bipartite
+ * graph G and pairs (s, t) with additive error eps, it returns r'(s,t) with
+ * |r'(s,t) - r(s,t)| <= eps with probability at least 1 - delta.
+ *
+ * The computation is Algorithm 3 (GEER): a per-pair maximum walk length l
+ * (Eq. ell, Theorem 3.1), l_b products with the transition matrix
+ * P = D^-1 A (Algorithm 2, SMM), then adaptive Monte Carlo walks from the SMM
+ * frontier (Algorithm 1, AMC) with the empirical-Bernstein stop rule
+ * (Lemma 3.2, Eq. fx) and the Hoeffding cap eta* (Eq. etas-star).
+ *
+ * Conventions for every entry point:
+ *   - All functions return GEER_OK (0) or a negative geer_status.  On error
+ *     nothing has been written to any output, and geer_last_error() returns a
+ *     thread-local message describing the failure.
+ *   - Host pointers are owned by the caller and are not retained after the
+ *     call returns.  Device pointers (the *_device variants) must be HIP
+ *     device allocations on the graph's device; the caller owns them.
+ *   - A geer_graph may be used by one host thread / one stream at a time.
+ *   - Node ids are 0-based int32.  The graph must be given in canonical CSR
+ *     form: symmetric, no self-loops, no duplicate entries, every degree >= 1,
+ *     each row sorted ascending.  The order of a row is part of the walk
+ *     definition (the next node of a walk at u is row u's
+ *     (draw mod d(u))-th entry).
+ *
+ * Walk randomness (the paper names no generator): Philox4x32-10 (Salmon,
+ * Moraes, Dror, Shaw, SC'11) with key (seed low word, seed high word) and
+ * counter (step >> 2, k, (batch << 1) | side, q).  step counts from 0 within
+ * a walk, k is the walk-pair index within AMC batch `batch` (0-based), side
+ * is 0 for the walk from s and 1 for the walk from t, and q is the query's
+ * index (its position in the call plus geer_params.qid_offset).  The draw of a
+ * step is output word (step & 3).  Walk node sequences are therefore integer
+ * exact and reproducible on any implementation of this specification.
+ */
+#ifndef GEER_H
+#define GEER_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GEER_OK = 0,
+    GEER_E_INVALID_ARG = -1,   /* bad size, pointer, eps, delta, tau, node id, ... */
+    GEER_E_GRAPH = -2,         /* CSR not canonical: asymmetric, self-loop, duplicate,
+                                  unsorted row, degree 0, bad offsets */
+    GEER_E_NOT_CONNECTED = -3, /* graph has more than one connected component */
+    GEER_E_BIPARTITE = -4,     /* lambda >= 1 (bipartite graph, Theorem 3.1 needs lambda < 1) */
+    GEER_E_NO_LAMBDA = -5,     /* query issued before lambda was set or computed */
+    GEER_E_OOM = -6,           /* device allocation failed or scratch cap exceeded */
+    GEER_E_DEVICE = -7,        /* a HIP runtime call failed */
+    GEER_E_MODEL = -8          /* learned-scheduler model missing, malformed or unusable */
+} geer_status;
+
+/* Opaque handles. */
+typedef struct geer_graph geer_graph;  /* device copy of the CSR + per-graph scratch */
+typedef struct geer_model geer_model;  /* learned-scheduler weights (host + device copies) */
+
+/* SMM depth schedule. */
+enum {
+    GEER_SCHEDULE_GREEDY = 0,  /* the paper's switch rule, Eq. (smm-amc) */
+    GEER_SCHEDULE_LEARNED = 1, /* l_b and tau from a geer_model; greedy is the fallback */
+    GEER_SCHEDULE_FIXED = 2    /* l_b = min(fixed_ell_b[q], l) for every query */
+};
+
+/* geer_params.flags */
+enum {
+    GEER_FLAG_FP64_VECTORS = 1u << 0, /* keep SMM vectors in FP64 instead of FP32 */
+    GEER_FLAG_NO_GRAPH_CAPTURE = 1u << 1 /* run AMC rounds eagerly instead of as a hipGraph */
+};
+
+typedef struct geer_params {
+    double delta;                /* failure probability, 0 < delta < 1 (default 0.01) */
+    int32_t tau;                 /* number of AMC batches, 1..30 (default 5) */
+    int32_t schedule;            /* GEER_SCHEDULE_* (default GREEDY) */
+    uint64_t seed;               /* Philox key (default 0) */
+    int64_t qid_offset;          /* added to a query's position to form its walk counter id */
+    const int32_t *fixed_ell_b;  /* FIXED: host array [nq] of requested SMM depths (>= 0) */
+    const geer_model *model;     /* LEARNED: the scheduler */
+    void *stream;                /* hipStream_t to run on, or NULL for the library's stream */
+    int32_t batch_queries;       /* queries per SMM batch, 1..64 (0 = 64) */
+    int32_t col_tile;            /* SpMM column tile 16/32/64/128 (0 = autotuned/default) */
+    int32_t walk_ilp;            /* walks interleaved per lane 1/2/4 (0 = autotuned/default) */
+    int32_t group_batches;       /* SMM batches resident before each AMC phase (0 = auto) */
+    uint32_t flags;              /* GEER_FLAG_* */
+    int32_t reserved[7];
+} geer_params;
+
+/* Per-query record (optional output of geer_query). */
+typedef struct geer_query_stats {
+    int32_t ell;          /* Eq. (ell) */
+    int32_t ell_b;        /* SMM products performed */
+    int32_t tau;          /* AMC batches allowed */
+    int32_t batches_run;  /* AMC batches performed */
+    int32_t stop_reason;  /* GEER_STOP_* */
+    int32_t fallback;     /* LEARNED: 1 if the greedy schedule was used instead */
+    int64_t eta1;         /* first AMC batch size (walk pairs) */
+    int64_t walk_pairs;   /* total walk pairs sampled */
+    int64_t supp_sum;     /* sum of degrees over the supports of the final SMM vectors */
+    double r_b;           /* deterministic part (hops 0..l_b) */
+    double r_f;           /* Monte Carlo part (AMC estimate) */
+    double psi;           /* Eq. (Delta-st) */
+    double eta_star;      /* Eq. (etas-star) */
+    double sigma2;        /* empirical variance of the last batch */
+    double f_last;        /* Bernstein half-width of the last batch, Eq. (fx) */
+} geer_query_stats;
+
+enum {
+    GEER_STOP_SAME_NODE = 0,  /* s == t, r = 0 */
+    GEER_STOP_NO_WALKS = 1,   /* l_f = l - l_b == 0: nothing left to sample */
+    GEER_STOP_BERNSTEIN = 2,  /* f(eta, sigma^2, psi, delta/tau) <= eps/2 */
+    GEER_STOP_CAP = 3         /* batch tau reached (eta >= eta*, Hoeffding) */
+};
+
+/* Fill *p with the defaults listed above. */
+geer_status geer_params_default(geer_params *p);
+
+/* Copy a canonical CSR graph to the current HIP device.
+ * n: node count (>= 2).  row_ptr: host int32[n+1], row_ptr[0] == 0, non-decreasing.
+ * col_idx: host int32[row_ptr[n]].  flags: 0, or 1 to skip the O(nnz log d)
+ * canonical-form and connectivity checks (the caller vouches for them).
+ * Returns GEER_E_GRAPH / GEER_E_NOT_CONNECTED for invalid input. */
+geer_status geer_graph_create(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                              uint32_t flags, geer_graph **out);
+
+/* Free the graph and all device memory it owns.  NULL is ignored. */
+void geer_graph_destroy(geer_graph *g);
+
+/* lambda = max(|lambda_2|, |lambda_n|) of P (Theorem 3.1), a per-graph
+ * preprocessing value (Section 3.1).  Must satisfy 0 <= lambda < 1
+ * (lambda >= 1 -> GEER_E_BIPARTITE). */
+geer_status geer_graph_set_lambda(geer_graph *g, double lambda);
+geer_status geer_graph_get_lambda(const geer_graph *g, double *lambda_out);
+
+/* Estimate lambda on the GPU by Lanczos on D^-1/2 A D^-1/2 with the top
+ * eigenvector sqrt(d) deflated, full reorthogonalisation, and the extreme Ritz
+ * values widened by their residual norms (a conservative upper estimate).
+ * Stores the value in the graph (as geer_graph_set_lambda) and returns it.
+ * max_iter: Krylov dimension (e.g. 300).  tol: stop once both extreme
+ * residual norms are below tol. */
+geer_status geer_graph_compute_lambda(geer_graph *g, int32_t max_iter, double tol,
+                                      uint64_t seed, double *lambda_out);
+
+/* Graph facts: n, nnz (directed CSR entries), max degree. */
+geer_status geer_graph_info(const geer_graph *g, int32_t *n, int64_t *nnz, int32_t *max_degree);
+
+/* Answer nq queries (Algorithm 3).  s, t: host int32[nq]; eps: host double[nq]
+ * (each > 0, finite).  params may be NULL (defaults).  r_out: host double[nq].
+ * stats: host geer_query_stats[nq] or NULL.  Blocks until the results are in
+ * host memory. */
+geer_status geer_query(geer_graph *g, int64_t nq, const int32_t *s, const int32_t *t,
+                       const double *eps, const geer_params *params, double *r_out,
+                       geer_query_stats *stats);
+
+/* As geer_query with device inputs and outputs, enqueued on params->stream
+ * (or the library stream).  d_s, d_t: device int32[nq]; d_eps: device
+ * double[nq]; d_r_out: device double[nq]; d_stats: device
+ * geer_query_stats[nq] or NULL.  Node ids and eps are validated on the device;
+ * an invalid entry makes the call return GEER_E_INVALID_ARG after the stream
+ * has drained (outputs then hold NaN for the invalid queries).  The call
+ * returns when the work has finished. */
+geer_status geer_query_device(geer_graph *g, int64_t nq, const int32_t *d_s, const int32_t *d_t,
+                              const double *d_eps, const geer_params *params, double *d_r_out,
+                              geer_query_stats *d_stats);
+
+/* ---- Phase-level entry points (same kernels as geer_query) ------------- */
+
+/* SMM (Algorithm 2) for one batch of nq <= 64 pairs, exactly `hops` products.
+ * vec_out: host buffer of n * 2 * nq values (double if GEER_FLAG_FP64_VECTORS
+ * is in flags, else float), node-major: entry [v * 2nq + 2j] is s*_j(v) and
+ * [v * 2nq + 2j + 1] is t*_j(v).  rb_out: host double[nq], r_b after the hops.
+ * top2_out: host double[4 * nq] = (max1 s*, max2 s*, max1 t*, max2 t*) per pair.
+ * supp_out: host int64[2 * nq], degree sums over the structural supports of
+ * s*_j and t*_j.  Any of the outputs except vec_out may be NULL. */
+geer_status geer_smm(geer_graph *g, int32_t nq, const int32_t *s, const int32_t *t, int32_t hops,
+                     uint32_t flags, int32_t col_tile, void *vec_out, double *rb_out,
+                     double *top2_out, int64_t *supp_out);
+
+/* Record walk node sequences w_1..w_lf with the AMC walk sampler.
+ * For walk i: start[i], query id q[i], batch[i], pair index k[i], side[i].
+ * trace_out: host int32[nw * lf], row i holds walk i. */
+geer_status geer_walk_traces(geer_graph *g, int32_t nw, const int32_t *start, const uint32_t *q,
+                             const uint32_t *batch, const uint32_t *k, const uint32_t *side,
+                             int32_t lf, uint64_t seed, int32_t *trace_out);
+
+/* Algorithm 1 (AMC) for one pair with caller-supplied non-negative vectors
+ * x (for s) and y (for t): host double[n] each (converted to the vector type
+ * of flags).  Writes r_f and fills *stats (ell fields set to -1). */
+geer_status geer_amc(geer_graph *g, int32_t s, int32_t t, const double *x, const double *y,
+                     double eps, int32_t lf, int32_t tau, double delta, uint64_t seed, uint32_t q,
+                     uint32_t flags, double *rf_out, geer_query_stats *stats);
+
+/* Thread-local description of the last non-OK status on this thread. */
+const char *geer_last_error(void);
+
+/* Library version string. */
+const char *geer_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GEER_H */
