@@ -1,0 +1,311 @@
+// AMC phase (Algorithm 1 as called from Algorithm 3): adaptive batches of
+// walk pairs from the SMM frontier, stopped by the empirical-Bernstein rule.
+//
+// Work decomposition: in batch i a query needs eta_i = eta_1 * 2^i walk
+// pairs.  Pairs are cut into chunks of 32; a wavefront takes one chunk
+// (lanes 2k and 2k+1 walk S_k from s and T_k from t).  Chunk offsets come
+// from a prefix sum over the group's queries, so a persistent grid can
+// stride over all chunks of all queries of a group in one launch.  Each chunk
+// writes (sum Z, sum Z^2) to its own slot and the stop kernel adds the slots
+// of a query in a fixed order: results do not depend on scheduling.
+#include "geer_internal.h"
+
+namespace geer {
+
+template <class T> struct Val2;
+template <> struct Val2<float> { using type = float2; };
+template <> struct Val2<double> { using type = double2; };
+
+// ----------------------------------------------------------------------------
+// plan: chunk prefix sums for batch `round` of the active queries of a group
+// ----------------------------------------------------------------------------
+
+__global__ __launch_bounds__(1024) void k_amc_plan(QState qs, int64_t q0, int nq, int round,
+                                                   int64_t *__restrict__ chunk_off,
+                                                   int64_t *__restrict__ total,
+                                                   int32_t *__restrict__ overflow)
+{
+    __shared__ int64_t s_sum[1024];
+    const int tid = threadIdx.x;
+    const int per = (nq + 1023) / 1024;
+    const int a = min(nq, tid * per), b = min(nq, a + per);
+    int64_t local = 0;
+    for (int i = a; i < b; ++i) {
+        int64_t q = q0 + i;
+        if (qs.active_amc[q]) {
+            int64_t eta = qs.eta1[q] << round;
+            if (eta >= (int64_t(1) << 32)) *overflow = 1;
+            local += (eta + kPairsPerChunk - 1) / kPairsPerChunk;
+        }
+    }
+    s_sum[tid] = local;
+    __syncthreads();
+    // inclusive Hillis-Steele scan over the 1024 per-thread sums
+    for (int o = 1; o < 1024; o <<= 1) {
+        int64_t v = tid >= o ? s_sum[tid - o] : 0;
+        __syncthreads();
+        s_sum[tid] += v;
+        __syncthreads();
+    }
+    int64_t run = s_sum[tid] - local;  // exclusive prefix of this thread's range
+    for (int i = a; i < b; ++i) {
+        chunk_off[i] = run;
+        int64_t q = q0 + i;
+        if (qs.active_amc[q]) {
+            int64_t eta = qs.eta1[q] << round;
+            run += (eta + kPairsPerChunk - 1) / kPairsPerChunk;
+        }
+    }
+    if (tid == 1023) {
+        chunk_off[nq] = s_sum[1023];
+        *total = s_sum[1023];
+    }
+}
+
+// ----------------------------------------------------------------------------
+// walks
+// ----------------------------------------------------------------------------
+
+template <class T>
+__global__ __launch_bounds__(256) void k_walk(QState qs, int64_t q0, int nq, int round,
+                                              const int64_t *__restrict__ chunk_off,
+                                              const int64_t *__restrict__ total_p,
+                                              const int32_t *__restrict__ row_ptr,
+                                              const int32_t *__restrict__ col_idx,
+                                              const T *__restrict__ pool, uint32_t key0,
+                                              uint32_t key1, int64_t qid_offset,
+                                              double2 *__restrict__ zpart)
+{
+    using T2 = typename Val2<T>::type;
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    const int64_t total = *total_p;
+    const uint32_t side = lane & 1;
+    for (int64_t c = gw; c < total; c += nw) {
+        // query of this chunk: largest i with chunk_off[i] <= c
+        int lo = 0, hi = nq;
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (chunk_off[mid] <= c) lo = mid;
+            else hi = mid;
+        }
+        const int64_t q = q0 + lo;
+        const int64_t eta = qs.eta1[q] << round;
+        const int64_t k = (c - chunk_off[lo]) * kPairsPerChunk + (lane >> 1);
+        const bool valid = k < eta;
+        const int32_t s = qs.s[q], t = qs.t[q];
+        const int32_t lf = qs.lf[q];
+        const int64_t voff = qs.vec_off[q];
+        const double ids = 1.0 / (row_ptr[s + 1] - row_ptr[s]);
+        const double idt = 1.0 / (row_ptr[t + 1] - row_ptr[t]);
+        const uint32_t qid = (uint32_t)(q + qid_offset);
+        const uint32_t c2 = ((uint32_t)round << 1) | side;
+        double acc = 0.0;
+        if (valid) {
+            int32_t u = side ? t : s;
+            uint4 r4 = make_uint4(0, 0, 0, 0);
+            for (int32_t step = 0; step < lf; ++step) {
+                if ((step & 3) == 0)
+                    r4 = philox4x32_10(make_uint4((uint32_t)step >> 2, (uint32_t)k, c2, qid),
+                                       key0, key1);
+                u = walk_next(row_ptr, col_idx, u, pick_word(r4, (uint32_t)step & 3u));
+                double xv, yv;
+                if (voff < 0) {
+                    xv = u == s ? 1.0 : 0.0;
+                    yv = u == t ? 1.0 : 0.0;
+                } else {
+                    T2 w = *reinterpret_cast<const T2 *>(pool + voff + (size_t)u * kCols);
+                    xv = (double)w.x;
+                    yv = (double)w.y;
+                }
+                // Z_k: S_k adds s(u)/d(s) - t(u)/d(t); T_k adds t(u)/d(t) - s(u)/d(s)
+                acc += side ? (yv * idt - xv * ids) : (xv * ids - yv * idt);
+            }
+        }
+        const double z = acc + __shfl_xor(acc, 1);
+        double zs = (valid && side == 0) ? z : 0.0;
+        double z2 = zs * zs;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            zs += __shfl_xor(zs, o);
+            z2 += __shfl_xor(z2, o);
+        }
+        if (lane == 0) zpart[c] = make_double2(zs, z2);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// stop rule after batch `round` (one wavefront per query)
+// ----------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_amc_stop(QState qs, int64_t q0, int nq, int round,
+                                                  const int64_t *__restrict__ chunk_off,
+                                                  const double2 *__restrict__ zpart, int32_t tau,
+                                                  double delta)
+{
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= nq) return;
+    const int64_t q = q0 + i;
+    if (!qs.active_amc[q]) return;
+    double zs = 0.0, z2 = 0.0;
+    for (int64_t c = chunk_off[i] + lane; c < chunk_off[i + 1]; c += 64) {
+        double2 p = zpart[c];
+        zs += p.x;
+        z2 += p.y;
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        zs += __shfl_xor(zs, o);
+        z2 += __shfl_xor(z2, o);
+    }
+    if (lane != 0) return;
+    const double eta = (double)(qs.eta1[q] << round);
+    const double z = zs / eta;
+    double var = z2 / eta - z * z;
+    if (var < 0.0) var = 0.0;
+    const double f = bernstein_of(eta, var, qs.psi[q], delta / (double)tau);
+    qs.batches[q] = round + 1;
+    qs.walk_pairs[q] += qs.eta1[q] << round;
+    qs.zsum[q] = zs;
+    qs.z2sum[q] = z2;
+    qs.var[q] = var;
+    qs.f[q] = f;
+    qs.rf[q] = z;
+    if (f <= qs.eps[q] / 2.0) {
+        qs.active_amc[q] = 0;
+        qs.stop[q] = GEER_STOP_BERNSTEIN;
+    } else if (round + 1 >= tau) {
+        qs.active_amc[q] = 0;
+        qs.stop[q] = GEER_STOP_CAP;
+    }
+}
+
+geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hipStream_t st,
+                      int walk_ilp)
+{
+    (void)walk_ilp;
+    Workspace &ws = g->ws;
+    if (grp.nq <= 0) return GEER_OK;
+    const int nq = (int)grp.nq;
+    GEER_TRY(ws.chunk_off.reserve(((size_t)nq + 1) * sizeof(int64_t)));
+    int64_t *chunk_off = ws.chunk_off.as<int64_t>();
+    int64_t *d_total = ws.misc.as<int64_t>() + 8;
+    int32_t *d_over = reinterpret_cast<int32_t *>(ws.misc.as<int64_t>() + 9);
+    GEER_HIP(hipMemsetAsync(d_over, 0, sizeof(int32_t), st));
+    const uint32_t key0 = (uint32_t)c.seed, key1 = (uint32_t)(c.seed >> 32);
+    for (int round = 0; round < c.tau; ++round) {
+        hipLaunchKernelGGL(k_amc_plan, dim3(1), dim3(1024), 0, st, c.qs, grp.q0, nq, round,
+                           chunk_off, d_total, d_over);
+        GEER_HIP(hipGetLastError());
+        int64_t host[2] = {0, 0};
+        GEER_HIP(hipMemcpyAsync(host, d_total, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        GEER_HIP(hipStreamSynchronize(st));
+        if (((int32_t *)&host[1])[0] != 0)
+            return fail(GEER_E_INVALID_ARG, "AMC batch exceeds 2^32 walk pairs for a query");
+        const int64_t total = host[0];
+        if (total == 0) break;
+        GEER_TRY(ws.zpart.reserve((size_t)total * sizeof(double2)));
+        const int64_t want_blocks = (total + 3) / 4;
+        const int blocks = (int)std::min<int64_t>(want_blocks, (int64_t)g->num_cus * 16);
+        if (grp.value_size == 4)
+            hipLaunchKernelGGL(k_walk<float>, dim3(blocks), dim3(256), 0, st, c.qs, grp.q0, nq,
+                               round, chunk_off, d_total, g->d_row_ptr, g->d_col_idx,
+                               (const float *)grp.pool, key0, key1, c.qid_offset,
+                               ws.zpart.as<double2>());
+        else
+            hipLaunchKernelGGL(k_walk<double>, dim3(blocks), dim3(256), 0, st, c.qs, grp.q0, nq,
+                               round, chunk_off, d_total, g->d_row_ptr, g->d_col_idx,
+                               (const double *)grp.pool, key0, key1, c.qid_offset,
+                               ws.zpart.as<double2>());
+        GEER_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_amc_stop, dim3((nq + 3) / 4), dim3(256), 0, st, c.qs, grp.q0, nq,
+                           round, chunk_off, ws.zpart.as<double2>(), c.tau, c.delta);
+        GEER_HIP(hipGetLastError());
+    }
+    return GEER_OK;
+}
+
+// ----------------------------------------------------------------------------
+// combine r' = r_b + r_f and write the per-query records
+// ----------------------------------------------------------------------------
+
+__global__ void k_finalize(QState qs, int64_t nq, double *__restrict__ r_out,
+                           geer_query_stats *__restrict__ stats)
+{
+    int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    double r;
+    if (qs.stop[q] < 0) r = __builtin_nan("");
+    else if (qs.stop[q] == GEER_STOP_SAME_NODE) r = 0.0;
+    else r = qs.rb[q] + qs.rf[q];
+    qs.r[q] = r;
+    r_out[q] = r;
+    if (stats) {
+        geer_query_stats st;
+        st.ell = qs.ell[q];
+        st.ell_b = qs.lb[q];
+        st.tau = qs.tau_q[q];
+        st.batches_run = qs.batches[q];
+        st.stop_reason = qs.stop[q];
+        st.fallback = qs.fallback[q];
+        st.eta1 = qs.eta1[q];
+        st.walk_pairs = qs.walk_pairs[q];
+        st.supp_sum = qs.supp_sum[q];
+        st.r_b = qs.stop[q] == GEER_STOP_SAME_NODE ? 0.0 : qs.rb[q];
+        st.r_f = qs.rf[q];
+        st.psi = qs.psi[q];
+        st.eta_star = qs.eta_star[q];
+        st.sigma2 = qs.var[q];
+        st.f_last = qs.f[q];
+        stats[q] = st;
+    }
+}
+
+geer_status launch_finalize(geer_graph *g, const QueryCtx &c, double *d_r_out,
+                            geer_query_stats *d_stats, hipStream_t st)
+{
+    (void)g;
+    if (c.nq == 0) return GEER_OK;
+    hipLaunchKernelGGL(k_finalize, dim3((int)((c.nq + 255) / 256)), dim3(256), 0, st, c.qs, c.nq,
+                       d_r_out, d_stats);
+    GEER_HIP(hipGetLastError());
+    return GEER_OK;
+}
+
+// ----------------------------------------------------------------------------
+// walk traces (same sampler as k_walk)
+// ----------------------------------------------------------------------------
+
+__global__ void k_walk_traces(int32_t nw, const int32_t *__restrict__ start,
+                              const uint32_t *__restrict__ qv, const uint32_t *__restrict__ bv,
+                              const uint32_t *__restrict__ kv, const uint32_t *__restrict__ sv,
+                              int32_t lf, uint32_t key0, uint32_t key1,
+                              const int32_t *__restrict__ row_ptr,
+                              const int32_t *__restrict__ col_idx, int32_t *__restrict__ trace)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nw) return;
+    int32_t u = start[i];
+    const uint32_t c1 = kv[i], c2 = (bv[i] << 1) | sv[i], c3 = qv[i];
+    uint4 r4 = make_uint4(0, 0, 0, 0);
+    for (int32_t step = 0; step < lf; ++step) {
+        if ((step & 3) == 0) r4 = philox4x32_10(make_uint4((uint32_t)step >> 2, c1, c2, c3), key0, key1);
+        u = walk_next(row_ptr, col_idx, u, pick_word(r4, (uint32_t)step & 3u));
+        trace[(size_t)i * lf + step] = u;
+    }
+}
+
+geer_status launch_walk_traces(geer_graph *g, int32_t nw, const int32_t *start, const uint32_t *q,
+                               const uint32_t *batch, const uint32_t *k, const uint32_t *side,
+                               int32_t lf, uint64_t seed, int32_t *trace, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_walk_traces, dim3((nw + 255) / 256), dim3(256), 0, st, nw, start, q,
+                       batch, k, side, lf, (uint32_t)seed, (uint32_t)(seed >> 32), g->d_row_ptr,
+                       g->d_col_idx, trace);
+    GEER_HIP(hipGetLastError());
+    return GEER_OK;
+}
+
+}  // namespace geer

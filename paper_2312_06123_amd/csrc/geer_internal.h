@@ -1,0 +1,249 @@
+// Internal declarations of the MI355X GEER library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/geer.h"
+
+// ----------------------------------------------------------------------------
+// Error plumbing
+// ----------------------------------------------------------------------------
+
+namespace geer {
+
+void set_error(const std::string &msg);
+geer_status fail(geer_status st, const std::string &msg);
+
+#define GEER_HIP(call)                                                                 \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return ::geer::fail(GEER_E_DEVICE, std::string(#call) + ": " +             \
+                                                   hipGetErrorString(e_));             \
+    } while (0)
+
+#define GEER_TRY(expr)                                                                 \
+    do {                                                                               \
+        geer_status s_ = (expr);                                                       \
+        if (s_ != GEER_OK) return s_;                                                  \
+    } while (0)
+
+// ----------------------------------------------------------------------------
+// Fixed layout constants
+// ----------------------------------------------------------------------------
+
+constexpr int kCols = 128;            // vector columns per SMM batch slot (64 pairs x {s, t})
+constexpr int kMaxPairs = kCols / 2;  // pairs per SMM batch
+constexpr int kBitWords = kCols / 32; // support bitmask words per node
+constexpr int kSegNnz = 256;          // rows longer than this are split into segments
+constexpr int kPairsPerChunk = 32;    // walk pairs per wavefront work item (64 lanes)
+
+// ----------------------------------------------------------------------------
+// Device-resident growable buffer
+// ----------------------------------------------------------------------------
+
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    geer_status reserve(size_t want);
+    void release();
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// ----------------------------------------------------------------------------
+// Per-query device state (structure of arrays, one allocation)
+// ----------------------------------------------------------------------------
+
+struct QState {
+    int32_t *s, *t, *ell, *lb, *lb_target, *lf, *batches, *stop, *active_smm, *active_amc,
+        *fallback, *tau_q;
+    int64_t *eta1, *walk_pairs, *supp_sum, *vec_off;
+    double *eps, *rb, *psi, *eta_star, *zsum, *z2sum, *var, *f, *rf, *r;
+};
+
+struct Workspace {
+    DevBuf pool;      // SMM vectors: slots x {H1, A, B} x n x kCols values
+    DevBuf bits;      // structural supports: slots x {H1, A, B} x n x kBitWords
+    DevBuf part;      // per-block column statistics (max1, max2 as double; degree sums)
+    DevBuf segbuf;    // heavy-row segment partial sums (values + bits)
+    DevBuf colstat;   // per-column reduced statistics for the current hop
+    DevBuf qstate;    // QState arrays
+    DevBuf chunk_off; // AMC: chunk prefix sums per group query
+    DevBuf zpart;     // AMC: per-chunk (sum Z, sum Z^2)
+    DevBuf misc;      // small scalars (active masks, totals)
+    DevBuf io;        // staging for host inputs/outputs
+    int slots = 0;
+    int value_size = 0;
+    int64_t nq_cap = 0;
+};
+
+}  // namespace geer
+
+// ----------------------------------------------------------------------------
+// The opaque graph handle
+// ----------------------------------------------------------------------------
+
+struct geer_graph {
+    int device = 0;
+    int32_t n = 0;
+    int64_t nnz = 0;
+    int32_t max_deg = 0;
+    double lambda = -1.0;
+    bool has_lambda = false;
+    hipStream_t stream = nullptr;
+    int num_cus = 0;
+    // CSR on device
+    int32_t *d_row_ptr = nullptr;
+    int32_t *d_col_idx = nullptr;
+    float *d_inv_deg_f = nullptr;
+    double *d_inv_deg_d = nullptr;
+    // SpMM work decomposition: light rows (degree <= kSegNnz) sorted by
+    // degree descending, heavy rows split into segments of <= kSegNnz entries
+    int32_t *d_light_rows = nullptr;
+    int32_t n_light = 0;
+    int32_t *d_heavy_rows = nullptr;
+    int32_t *d_heavy_seg_start = nullptr;  // [n_heavy + 1] first segment of each heavy row
+    int32_t n_heavy = 0;
+    int32_t *d_seg_begin = nullptr;        // [n_seg] first CSR entry of each segment
+    int32_t *d_seg_end = nullptr;          // [n_seg] one past the last entry
+    int32_t n_seg = 0;
+    geer::Workspace ws;
+};
+
+// ----------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and the walk sampler.
+// Shared by every kernel that draws a walk so that traces and AMC walks are
+// the same function of (seed, q, batch, k, side, step).
+// ----------------------------------------------------------------------------
+
+namespace geer {
+
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+        uint32_t hi0 = __umulhi(m0, c.x), lo0 = m0 * c.x;
+        uint32_t hi1 = __umulhi(m1, c.z), lo1 = m1 * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+__device__ __forceinline__ uint32_t pick_word(const uint4 &r, uint32_t i)
+{
+    return i == 0 ? r.x : (i == 1 ? r.y : (i == 2 ? r.z : r.w));
+}
+
+// One step of a walk: the next node is row u's (draw mod d(u))-th CSR entry.
+__device__ __forceinline__ int32_t walk_next(const int32_t *__restrict__ row_ptr,
+                                             const int32_t *__restrict__ col_idx, int32_t u,
+                                             uint32_t draw)
+{
+    int32_t b = row_ptr[u];
+    uint32_t d = (uint32_t)(row_ptr[u + 1] - b);
+    return col_idx[b + (int32_t)(draw % d)];
+}
+
+// ----------------------------------------------------------------------------
+// Scalar formulas (FP64), same readings as documented in the design notes.
+// ----------------------------------------------------------------------------
+
+// Eq. (ell), Theorem 3.1, clamped at 0.
+__host__ __device__ inline int32_t ell_of(double ds, double dt, double eps, double lambda)
+{
+    if (!(lambda > 0.0)) return 0;
+    double v = log((2.0 / ds + 2.0 / dt) / (eps * (1.0 - lambda))) / log(1.0 / lambda) - 1.0;
+    double c = ceil(v);
+    return c < 0.0 ? 0 : (int32_t)c;
+}
+
+// Eq. (Delta-st).
+__host__ __device__ inline double psi_of(int32_t lf, double m1s, double m2s, double m1t,
+                                         double m2t, double ids, double idt)
+{
+    double up = (double)((lf + 1) / 2), dn = (double)(lf / 2);
+    return 2.0 * up * (m1s * ids + m1t * idt) + 2.0 * dn * (m2s * ids + m2t * idt);
+}
+
+// Eq. (etas-star).
+__host__ __device__ inline double eta_star_of(double psi, double eps, int32_t tau, double delta)
+{
+    return 2.0 * psi * psi * log(2.0 * (double)tau / delta) / (eps * eps);
+}
+
+// First AMC batch: ceil(eta* / 2^(tau-1)).
+__host__ __device__ inline int64_t eta1_of(double eta_star, int32_t tau)
+{
+    double v = ceil(eta_star / ldexp(1.0, tau - 1));
+    return v <= 0.0 ? 0 : (int64_t)v;
+}
+
+// Eq. (fx), empirical Bernstein half-width.
+__host__ __device__ inline double bernstein_of(double nz, double var, double psi, double delta)
+{
+    double lg = log(3.0 / delta);
+    return sqrt(2.0 * var * lg / nz) + 3.0 * psi * lg / nz;
+}
+
+// ----------------------------------------------------------------------------
+// Kernel launchers (defined in smm.hip / amc.hip)
+// ----------------------------------------------------------------------------
+
+struct HopArgs {
+    const void *in;          // n x kCols values (previous hop)
+    void *out;               // n x kCols values (this hop)
+    const uint32_t *in_bits; // n x kBitWords
+    uint32_t *out_bits;
+    const uint64_t *mask;    // active pairs of the batch (bit j = pair j)
+    int col0, col_tile;      // column slice of this launch
+};
+
+struct QueryCtx {
+    QState qs;
+    int64_t nq;
+    double lambda, delta;
+    int32_t tau, schedule;
+    uint64_t seed;
+    int64_t qid_offset;
+};
+
+geer_status launch_init_queries(geer_graph *g, const QueryCtx &c, const int32_t *d_fixed,
+                                int32_t forced_hops, hipStream_t st);
+geer_status launch_hop1(geer_graph *g, const QueryCtx &c, int64_t q0, int nb, void *h1,
+                        uint32_t *h1_bits, const uint64_t *mask, int value_size, bool clear,
+                        hipStream_t st);
+geer_status launch_hop_dense(geer_graph *g, const HopArgs &a, int value_size, hipStream_t st);
+geer_status launch_epilogue(geer_graph *g, const QueryCtx &c, int64_t q0, int nb, int hop,
+                            const void *vec, int64_t vec_elem_off, uint64_t *mask,
+                            int value_size, int dense, hipStream_t st);
+geer_status launch_column_top2(geer_graph *g, const void *vec, int ncols, int value_size,
+                               hipStream_t st);
+
+struct AmcGroup {
+    int64_t q0;      // first query of the group
+    int64_t nq;      // queries in the group
+    const void *pool;
+    int value_size;
+};
+
+geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hipStream_t st,
+                      int walk_ilp);
+geer_status launch_finalize(geer_graph *g, const QueryCtx &c, double *d_r_out,
+                            geer_query_stats *d_stats, hipStream_t st);
+geer_status launch_walk_traces(geer_graph *g, int32_t nw, const int32_t *start, const uint32_t *q,
+                               const uint32_t *batch, const uint32_t *k, const uint32_t *side,
+                               int32_t lf, uint64_t seed, int32_t *trace, hipStream_t st);
+
+// Workspace helpers (query.hip)
+geer_status ensure_qstate(geer_graph *g, int64_t nq, QState *qs);
+geer_status ensure_slots(geer_graph *g, int slots, int value_size);
+int grid_blocks_dense(const geer_graph *g);
+
+}  // namespace geer

@@ -1,0 +1,234 @@
+// Graph residency: validation of the canonical CSR, upload to HBM, inverse
+// degrees, and the SpMM work decomposition (light rows / heavy-row segments).
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "geer_internal.h"
+
+namespace geer {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+geer_status fail(geer_status st, const std::string &msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+geer_status DevBuf::reserve(size_t want)
+{
+    if (want <= bytes) return GEER_OK;
+    release();
+    size_t cap = want + want / 8 + 256;
+    hipError_t e = hipMalloc(&ptr, cap);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        (void)hipGetLastError();
+        return fail(GEER_E_OOM, "device allocation of " + std::to_string(cap) + " bytes failed");
+    }
+    bytes = cap;
+    return GEER_OK;
+}
+
+void DevBuf::release()
+{
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+}  // namespace geer
+
+using namespace geer;
+
+static geer_status validate_csr(int32_t n, const int32_t *rp, const int32_t *ci)
+{
+    if (rp[0] != 0) return fail(GEER_E_GRAPH, "row_ptr[0] must be 0");
+    for (int32_t v = 0; v < n; ++v) {
+        if (rp[v + 1] < rp[v]) return fail(GEER_E_GRAPH, "row_ptr must be non-decreasing");
+        if (rp[v + 1] == rp[v])
+            return fail(GEER_E_GRAPH, "node " + std::to_string(v) + " has degree 0");
+    }
+    for (int32_t v = 0; v < n; ++v) {
+        for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+            int32_t u = ci[e];
+            if (u < 0 || u >= n) return fail(GEER_E_GRAPH, "col_idx out of range");
+            if (u == v) return fail(GEER_E_GRAPH, "self-loop at node " + std::to_string(v));
+            if (e > rp[v] && ci[e - 1] >= u)
+                return fail(GEER_E_GRAPH, "row " + std::to_string(v) +
+                                              " not strictly ascending (unsorted or duplicate)");
+            if (!std::binary_search(ci + rp[u], ci + rp[u + 1], v))
+                return fail(GEER_E_GRAPH, "graph is not symmetric (" + std::to_string(v) + "," +
+                                              std::to_string(u) + ")");
+        }
+    }
+    // connectivity: breadth-first search from node 0
+    std::vector<int32_t> queue;
+    queue.reserve(n);
+    std::vector<char> seen(n, 0);
+    queue.push_back(0);
+    seen[0] = 1;
+    for (size_t h = 0; h < queue.size(); ++h) {
+        int32_t u = queue[h];
+        for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+            int32_t w = ci[e];
+            if (!seen[w]) {
+                seen[w] = 1;
+                queue.push_back(w);
+            }
+        }
+    }
+    if ((int32_t)queue.size() != n)
+        return fail(GEER_E_NOT_CONNECTED, "graph is not connected (" +
+                                              std::to_string(queue.size()) + " of " +
+                                              std::to_string(n) + " nodes reachable from 0)");
+    return GEER_OK;
+}
+
+template <class T> static geer_status upload(T **dst, const T *src, size_t count)
+{
+    GEER_HIP(hipMalloc(dst, std::max<size_t>(count, 1) * sizeof(T)));
+    if (count) GEER_HIP(hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice));
+    return GEER_OK;
+}
+
+static geer_status build_graph(geer_graph *g, const int32_t *rp, const int32_t *ci)
+{
+    const int32_t n = g->n;
+    GEER_TRY(upload(&g->d_row_ptr, rp, (size_t)n + 1));
+    GEER_TRY(upload(&g->d_col_idx, ci, (size_t)g->nnz));
+    std::vector<float> invf(n);
+    std::vector<double> invd(n);
+    int32_t maxd = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        int32_t d = rp[v + 1] - rp[v];
+        maxd = std::max(maxd, d);
+        invd[v] = 1.0 / (double)d;
+        invf[v] = (float)invd[v];
+    }
+    g->max_deg = maxd;
+    GEER_TRY(upload(&g->d_inv_deg_f, invf.data(), invf.size()));
+    GEER_TRY(upload(&g->d_inv_deg_d, invd.data(), invd.size()));
+
+    // light rows sorted by degree descending (long rows first for load balance),
+    // heavy rows split into consecutive segments of at most kSegNnz entries
+    std::vector<int32_t> light, heavy, seg_start, seg_b, seg_e;
+    for (int32_t v = 0; v < n; ++v) {
+        int32_t d = rp[v + 1] - rp[v];
+        if (d > kSegNnz) heavy.push_back(v);
+        else light.push_back(v);
+    }
+    std::stable_sort(light.begin(), light.end(), [&](int32_t a, int32_t b) {
+        return rp[a + 1] - rp[a] > rp[b + 1] - rp[b];
+    });
+    seg_start.push_back(0);
+    for (int32_t v : heavy) {
+        for (int32_t b = rp[v]; b < rp[v + 1]; b += kSegNnz) {
+            seg_b.push_back(b);
+            seg_e.push_back(std::min(rp[v + 1], b + kSegNnz));
+        }
+        seg_start.push_back((int32_t)seg_b.size());
+    }
+    g->n_light = (int32_t)light.size();
+    g->n_heavy = (int32_t)heavy.size();
+    g->n_seg = (int32_t)seg_b.size();
+    GEER_TRY(upload(&g->d_light_rows, light.data(), light.size()));
+    GEER_TRY(upload(&g->d_heavy_rows, heavy.data(), heavy.size()));
+    GEER_TRY(upload(&g->d_heavy_seg_start, seg_start.data(), seg_start.size()));
+    GEER_TRY(upload(&g->d_seg_begin, seg_b.data(), seg_b.size()));
+    GEER_TRY(upload(&g->d_seg_end, seg_e.data(), seg_e.size()));
+    return GEER_OK;
+}
+
+extern "C" {
+
+const char *geer_last_error(void) { return g_last_error.c_str(); }
+
+const char *geer_version(void) { return "geer-mi355x 0.1 (gfx950)"; }
+
+geer_status geer_graph_create(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                              uint32_t flags, geer_graph **out)
+{
+    if (!out) return fail(GEER_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 2) return fail(GEER_E_INVALID_ARG, "n must be >= 2");
+    if (!row_ptr || !col_idx) return fail(GEER_E_INVALID_ARG, "row_ptr/col_idx is NULL");
+    if (row_ptr[n] < 0) return fail(GEER_E_GRAPH, "row_ptr[n] is negative");
+    if (!(flags & 1u)) GEER_TRY(validate_csr(n, row_ptr, col_idx));
+    geer_graph *g = new geer_graph();
+    g->n = n;
+    g->nnz = row_ptr[n];
+    if (hipGetDevice(&g->device) != hipSuccess) {
+        delete g;
+        return fail(GEER_E_DEVICE, "hipGetDevice failed (no GPU?)");
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, g->device) != hipSuccess) {
+        delete g;
+        return fail(GEER_E_DEVICE, "hipGetDeviceProperties failed");
+    }
+    g->num_cus = prop.multiProcessorCount;
+    if (hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete g;
+        return fail(GEER_E_DEVICE, "hipStreamCreate failed");
+    }
+    geer_status st = build_graph(g, row_ptr, col_idx);
+    if (st != GEER_OK) {
+        std::string msg = geer_last_error();
+        geer_graph_destroy(g);
+        return fail(st, msg);
+    }
+    *out = g;
+    return GEER_OK;
+}
+
+void geer_graph_destroy(geer_graph *g)
+{
+    if (!g) return;
+    (void)hipSetDevice(g->device);
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    void *ptrs[] = {g->d_row_ptr,    g->d_col_idx,    g->d_inv_deg_f,       g->d_inv_deg_d,
+                    g->d_light_rows, g->d_heavy_rows, g->d_heavy_seg_start, g->d_seg_begin,
+                    g->d_seg_end};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    DevBuf *bufs[] = {&g->ws.pool,  &g->ws.bits,      &g->ws.part,  &g->ws.segbuf,
+                      &g->ws.colstat, &g->ws.qstate, &g->ws.chunk_off, &g->ws.zpart,
+                      &g->ws.misc,  &g->ws.io};
+    for (DevBuf *b : bufs) b->release();
+    if (g->stream) (void)hipStreamDestroy(g->stream);
+    delete g;
+}
+
+geer_status geer_graph_set_lambda(geer_graph *g, double lambda)
+{
+    if (!g) return fail(GEER_E_INVALID_ARG, "graph is NULL");
+    if (!(lambda >= 0.0) || std::isnan(lambda))
+        return fail(GEER_E_INVALID_ARG, "lambda must be a number >= 0");
+    if (lambda >= 1.0) return fail(GEER_E_BIPARTITE, "lambda >= 1: graph is bipartite");
+    g->lambda = lambda;
+    g->has_lambda = true;
+    return GEER_OK;
+}
+
+geer_status geer_graph_get_lambda(const geer_graph *g, double *lambda_out)
+{
+    if (!g || !lambda_out) return fail(GEER_E_INVALID_ARG, "NULL argument");
+    if (!g->has_lambda) return fail(GEER_E_NO_LAMBDA, "lambda has not been set");
+    *lambda_out = g->lambda;
+    return GEER_OK;
+}
+
+geer_status geer_graph_info(const geer_graph *g, int32_t *n, int64_t *nnz, int32_t *max_degree)
+{
+    if (!g) return fail(GEER_E_INVALID_ARG, "graph is NULL");
+    if (n) *n = g->n;
+    if (nnz) *nnz = g->nnz;
+    if (max_degree) *max_degree = g->max_deg;
+    return GEER_OK;
+}
+
+}  // extern "C"

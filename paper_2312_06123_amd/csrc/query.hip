@@ -1,0 +1,593 @@
+// Query driver: batching of pairs into 64-pair SMM batches, groups of batches
+// resident in HBM before each AMC phase, and the C entry points.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "geer_internal.h"
+
+namespace geer {
+
+// misc scratch layout (int64 words): [0] active mask of the current batch,
+// [8] AMC chunk total, [9] AMC overflow flag
+static constexpr int kMiscWords = 16;
+
+geer_status ensure_qstate(geer_graph *g, int64_t nq, QState *qs)
+{
+    Workspace &ws = g->ws;
+    const int64_t cap = std::max<int64_t>(nq, 1);
+    const size_t per = 12 * sizeof(int32_t) + 4 * sizeof(int64_t) + 10 * sizeof(double);
+    GEER_TRY(ws.qstate.reserve((size_t)cap * per + 64));
+    GEER_TRY(ws.misc.reserve(kMiscWords * sizeof(int64_t)));
+    GEER_TRY(ws.colstat.reserve(kCols * (2 * sizeof(double) + sizeof(int64_t))));
+    char *p = ws.qstate.as<char>();
+    auto take = [&](auto *&dst, size_t elem) {
+        dst = reinterpret_cast<std::remove_reference_t<decltype(dst)>>(p);
+        p += (size_t)cap * elem;
+    };
+    // 8-byte fields first keeps every array aligned
+    take(qs->eta1, 8);
+    take(qs->walk_pairs, 8);
+    take(qs->supp_sum, 8);
+    take(qs->vec_off, 8);
+    take(qs->eps, 8);
+    take(qs->rb, 8);
+    take(qs->psi, 8);
+    take(qs->eta_star, 8);
+    take(qs->zsum, 8);
+    take(qs->z2sum, 8);
+    take(qs->var, 8);
+    take(qs->f, 8);
+    take(qs->rf, 8);
+    take(qs->r, 8);
+    take(qs->s, 4);
+    take(qs->t, 4);
+    take(qs->ell, 4);
+    take(qs->lb, 4);
+    take(qs->lb_target, 4);
+    take(qs->lf, 4);
+    take(qs->batches, 4);
+    take(qs->stop, 4);
+    take(qs->active_smm, 4);
+    take(qs->active_amc, 4);
+    take(qs->fallback, 4);
+    take(qs->tau_q, 4);
+    ws.nq_cap = cap;
+    return GEER_OK;
+}
+
+geer_status ensure_slots(geer_graph *g, int slots, int value_size)
+{
+    Workspace &ws = g->ws;
+    const size_t vals = (size_t)slots * 3 * (size_t)g->n * kCols;
+    const size_t words = (size_t)slots * 3 * (size_t)g->n * kBitWords;
+    const size_t vbytes = vals * (size_t)value_size, bbytes = words * sizeof(uint32_t);
+    bool grow = vbytes > ws.pool.bytes || bbytes > ws.bits.bytes;
+    if (grow || ws.value_size != value_size || ws.slots < slots) {
+        GEER_TRY(ws.pool.reserve(vbytes));
+        GEER_TRY(ws.bits.reserve(bbytes));
+        // H1 buffers must start (and are kept) all zero; clear everything once
+        GEER_HIP(hipMemset(ws.pool.ptr, 0, ws.pool.bytes));
+        GEER_HIP(hipMemset(ws.bits.ptr, 0, ws.bits.bytes));
+        ws.slots = slots;
+        ws.value_size = value_size;
+    }
+    return GEER_OK;
+}
+
+__global__ void k_batch_mask(QState qs, int64_t q0, int nb, uint64_t *mask)
+{
+    const int j = threadIdx.x;
+    bool a = j < nb && qs.active_smm[q0 + j];
+    unsigned long long m = __ballot(a);
+    if (j == 0) *mask = m;
+}
+
+struct SlotView {
+    char *pool;
+    uint32_t *bits;
+    size_t n;
+    int vs;
+    void *buf(int slot, int which) const
+    {
+        return pool + ((size_t)slot * 3 + which) * n * kCols * vs;
+    }
+    int64_t elem_off(int slot, int which) const { return ((int64_t)slot * 3 + which) * (int64_t)n * kCols; }
+    uint32_t *bw(int slot, int which) const { return bits + ((size_t)slot * 3 + which) * n * kBitWords; }
+};
+
+static int64_t host_mask(geer_graph *g, uint64_t *d_mask, hipStream_t st, geer_status *err)
+{
+    uint64_t m = 0;
+    if (hipMemcpyAsync(&m, d_mask, sizeof(m), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        *err = fail(GEER_E_DEVICE, "reading the batch mask failed");
+        return 0;
+    }
+    (void)g;
+    return (int64_t)m;
+}
+
+// SMM of one batch (pairs q0 .. q0+nb-1) in slot `slot`: hop 1 scatter, then
+// dense hops until every pair of the batch has stopped.  Returns the number
+// of hops performed.
+static geer_status smm_batch(geer_graph *g, const QueryCtx &c, const SlotView &sv, int slot,
+                             int64_t q0, int nb, int col_tile, int max_hops, hipStream_t st,
+                             int *hops_done)
+{
+    uint64_t *d_mask = reinterpret_cast<uint64_t *>(g->ws.misc.as<int64_t>());
+    hipLaunchKernelGGL(k_batch_mask, dim3(1), dim3(64), 0, st, c.qs, q0, nb, d_mask);
+    GEER_HIP(hipGetLastError());
+    *hops_done = 0;
+    geer_status err = GEER_OK;
+    if (host_mask(g, d_mask, st, &err) == 0) return err;
+    GEER_TRY(launch_hop1(g, c, q0, nb, sv.buf(slot, 0), sv.bw(slot, 0), d_mask, sv.vs, false, st));
+    GEER_TRY(launch_epilogue(g, c, q0, nb, 1, sv.buf(slot, 0), sv.elem_off(slot, 0), d_mask, sv.vs,
+                             0, st));
+    *hops_done = 1;
+    for (int hop = 2;; ++hop) {
+        int64_t m = host_mask(g, d_mask, st, &err);
+        if (err != GEER_OK) return err;
+        if (m == 0) break;
+        if (hop > max_hops)
+            return fail(GEER_E_DEVICE, "SMM batch still active after the largest possible l");
+        const int win = hop == 2 ? 0 : (hop % 2 == 0 ? 2 : 1);  // input buffer
+        const int wout = hop % 2 == 0 ? 1 : 2;                  // output buffer
+        HopArgs a;
+        a.in = sv.buf(slot, win);
+        a.out = sv.buf(slot, wout);
+        a.in_bits = sv.bw(slot, win);
+        a.out_bits = sv.bw(slot, wout);
+        a.mask = d_mask;
+        a.col0 = 0;
+        a.col_tile = col_tile;
+        GEER_TRY(launch_hop_dense(g, a, sv.vs, st));
+        GEER_TRY(launch_epilogue(g, c, q0, nb, hop, a.out, sv.elem_off(slot, wout), d_mask, sv.vs,
+                                 1, st));
+        *hops_done = hop;
+    }
+    return GEER_OK;
+}
+
+static int default_col_tile(const geer_graph *g, int vs)
+{
+    // keep one column tile of the vectors within the 256 MB last-level cache
+    const double tile_bytes_128 = (double)g->n * kCols * vs;
+    if (tile_bytes_128 <= 96e6) return 128;
+    if (tile_bytes_128 / 2 <= 96e6) return 64;
+    return 32;
+}
+
+static int default_group_batches(const geer_graph *g, int vs, int64_t nbatches)
+{
+    const double slot_bytes = 3.0 * g->n * kCols * vs;
+    int grp = (int)std::max(1.0, std::min(16.0, 48e9 / slot_bytes));
+    return (int)std::min<int64_t>(grp, std::max<int64_t>(nbatches, 1));
+}
+
+static geer_status check_params(const geer_params &p)
+{
+    if (!(p.delta > 0.0 && p.delta < 1.0)) return fail(GEER_E_INVALID_ARG, "delta must be in (0,1)");
+    if (p.tau < 1 || p.tau > 30) return fail(GEER_E_INVALID_ARG, "tau must be in 1..30");
+    if (p.schedule != GEER_SCHEDULE_GREEDY && p.schedule != GEER_SCHEDULE_FIXED &&
+        p.schedule != GEER_SCHEDULE_LEARNED)
+        return fail(GEER_E_INVALID_ARG, "unknown schedule");
+    if (p.batch_queries < 0 || p.batch_queries > kMaxPairs)
+        return fail(GEER_E_INVALID_ARG, "batch_queries must be in 0..64");
+    if (p.col_tile != 0 && p.col_tile != 32 && p.col_tile != 64 && p.col_tile != 128)
+        return fail(GEER_E_INVALID_ARG, "col_tile must be 0, 32, 64 or 128");
+    if (p.group_batches < 0) return fail(GEER_E_INVALID_ARG, "group_batches must be >= 0");
+    if (p.schedule == GEER_SCHEDULE_LEARNED && !p.model)
+        return fail(GEER_E_MODEL, "LEARNED schedule needs a model");
+    return GEER_OK;
+}
+
+// The whole query pipeline on device-resident inputs (already in qstate).
+static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
+                               const int32_t *d_fixed, double min_eps, hipStream_t st)
+{
+    // no pair can need more products than l of Eq. (ell) at d(s) = d(t) = 1
+    const int max_hops = ell_of(1.0, 1.0, min_eps, c.lambda);
+    const int vs = (p.flags & GEER_FLAG_FP64_VECTORS) ? 8 : 4;
+    const int B = p.batch_queries ? p.batch_queries : kMaxPairs;
+    const int64_t nbatches = (c.nq + B - 1) / B;
+    const int G = p.group_batches ? p.group_batches : default_group_batches(g, vs, nbatches);
+    const int col_tile = p.col_tile ? p.col_tile : default_col_tile(g, vs);
+    GEER_TRY(ensure_slots(g, G, vs));
+    GEER_TRY(launch_init_queries(g, c, d_fixed, -1, st));
+    SlotView sv{g->ws.pool.as<char>(), g->ws.bits.as<uint32_t>(), (size_t)g->n, vs};
+    for (int64_t b0 = 0; b0 < nbatches; b0 += G) {
+        const int64_t b1 = std::min<int64_t>(nbatches, b0 + G);
+        for (int64_t b = b0; b < b1; ++b) {
+            const int64_t q0 = b * B;
+            const int nb = (int)std::min<int64_t>(B, c.nq - q0);
+            int hops = 0;
+            GEER_TRY(smm_batch(g, c, sv, (int)(b - b0), q0, nb, col_tile, max_hops, st, &hops));
+        }
+        AmcGroup grp;
+        grp.q0 = b0 * B;
+        grp.nq = std::min<int64_t>(c.nq, b1 * B) - grp.q0;
+        grp.pool = sv.pool;
+        grp.value_size = vs;
+        GEER_TRY(amc_phase(g, c, grp, st, p.walk_ilp));
+        // restore the group's H1 buffers to all-zero
+        for (int64_t b = b0; b < b1; ++b) {
+            const int64_t q0 = b * B;
+            const int nb = (int)std::min<int64_t>(B, c.nq - q0);
+            GEER_TRY(launch_hop1(g, c, q0, nb, sv.buf((int)(b - b0), 0), sv.bw((int)(b - b0), 0),
+                                 nullptr, vs, true, st));
+        }
+    }
+    return GEER_OK;
+}
+
+static hipStream_t pick_stream(geer_graph *g, const geer_params &p)
+{
+    return p.stream ? (hipStream_t)p.stream : g->stream;
+}
+
+}  // namespace geer
+
+using namespace geer;
+
+extern "C" {
+
+geer_status geer_params_default(geer_params *p)
+{
+    if (!p) return fail(GEER_E_INVALID_ARG, "params is NULL");
+    std::memset(p, 0, sizeof(*p));
+    p->delta = 0.01;
+    p->tau = 5;
+    p->schedule = GEER_SCHEDULE_GREEDY;
+    return GEER_OK;
+}
+
+geer_status geer_query(geer_graph *g, int64_t nq, const int32_t *s, const int32_t *t,
+                       const double *eps, const geer_params *params, double *r_out,
+                       geer_query_stats *stats)
+{
+    if (!g) return fail(GEER_E_INVALID_ARG, "graph is NULL");
+    if (nq < 0) return fail(GEER_E_INVALID_ARG, "nq must be >= 0");
+    if (nq > 0 && (!s || !t || !eps || !r_out)) return fail(GEER_E_INVALID_ARG, "NULL array");
+    geer_params p;
+    if (params) p = *params;
+    else geer_params_default(&p);
+    GEER_TRY(check_params(p));
+    if (!g->has_lambda) return fail(GEER_E_NO_LAMBDA, "lambda has not been set");
+    if (p.schedule == GEER_SCHEDULE_FIXED && nq > 0 && !p.fixed_ell_b)
+        return fail(GEER_E_INVALID_ARG, "FIXED schedule needs fixed_ell_b");
+    for (int64_t i = 0; i < nq; ++i) {
+        if (s[i] < 0 || s[i] >= g->n || t[i] < 0 || t[i] >= g->n)
+            return fail(GEER_E_INVALID_ARG, "query " + std::to_string(i) + ": node out of range");
+        if (!(eps[i] > 0.0) || std::isinf(eps[i]))
+            return fail(GEER_E_INVALID_ARG, "query " + std::to_string(i) + ": eps must be > 0 and finite");
+    }
+    if (p.schedule == GEER_SCHEDULE_LEARNED)
+        return fail(GEER_E_MODEL, "learned scheduling is not available in this build");
+    if (nq == 0) return GEER_OK;
+    GEER_HIP(hipSetDevice(g->device));
+    hipStream_t st = pick_stream(g, p);
+    QueryCtx c;
+    GEER_TRY(ensure_qstate(g, nq, &c.qs));
+    c.nq = nq;
+    c.lambda = g->lambda;
+    c.delta = p.delta;
+    c.tau = p.tau;
+    c.schedule = p.schedule;
+    c.seed = p.seed;
+    c.qid_offset = p.qid_offset;
+    // stage inputs / outputs
+    const size_t io_bytes = (size_t)nq * (sizeof(double) + sizeof(int32_t) + sizeof(geer_query_stats)) + 256;
+    GEER_TRY(g->ws.io.reserve(io_bytes));
+    double *d_r = g->ws.io.as<double>();
+    int32_t *d_fixed = reinterpret_cast<int32_t *>(d_r + nq);
+    geer_query_stats *d_stats = reinterpret_cast<geer_query_stats *>(
+        (char *)g->ws.io.ptr + (((size_t)nq * (sizeof(double) + sizeof(int32_t)) + 15) / 16) * 16);
+    GEER_HIP(hipMemcpyAsync(c.qs.s, s, nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    GEER_HIP(hipMemcpyAsync(c.qs.t, t, nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    GEER_HIP(hipMemcpyAsync(c.qs.eps, eps, nq * sizeof(double), hipMemcpyHostToDevice, st));
+    if (p.schedule == GEER_SCHEDULE_FIXED)
+        GEER_HIP(hipMemcpyAsync(d_fixed, p.fixed_ell_b, nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    double min_eps = eps[0];
+    for (int64_t i = 1; i < nq; ++i) min_eps = std::min(min_eps, eps[i]);
+    GEER_TRY(run_queries(g, c, p, d_fixed, min_eps, st));
+    GEER_TRY(launch_finalize(g, c, d_r, stats ? d_stats : nullptr, st));
+    GEER_HIP(hipMemcpyAsync(r_out, d_r, nq * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (stats)
+        GEER_HIP(hipMemcpyAsync(stats, d_stats, nq * sizeof(geer_query_stats), hipMemcpyDeviceToHost, st));
+    GEER_HIP(hipStreamSynchronize(st));
+    return GEER_OK;
+}
+
+geer_status geer_query_device(geer_graph *g, int64_t nq, const int32_t *d_s, const int32_t *d_t,
+                              const double *d_eps, const geer_params *params, double *d_r_out,
+                              geer_query_stats *d_stats)
+{
+    if (!g) return fail(GEER_E_INVALID_ARG, "graph is NULL");
+    if (nq < 0) return fail(GEER_E_INVALID_ARG, "nq must be >= 0");
+    if (nq > 0 && (!d_s || !d_t || !d_eps || !d_r_out)) return fail(GEER_E_INVALID_ARG, "NULL array");
+    geer_params p;
+    if (params) p = *params;
+    else geer_params_default(&p);
+    GEER_TRY(check_params(p));
+    if (!g->has_lambda) return fail(GEER_E_NO_LAMBDA, "lambda has not been set");
+    if (p.schedule == GEER_SCHEDULE_FIXED && nq > 0 && !p.fixed_ell_b)
+        return fail(GEER_E_INVALID_ARG, "FIXED schedule needs fixed_ell_b");
+    if (p.schedule == GEER_SCHEDULE_LEARNED)
+        return fail(GEER_E_MODEL, "learned scheduling is not available in this build");
+    if (nq == 0) return GEER_OK;
+    GEER_HIP(hipSetDevice(g->device));
+    hipStream_t st = pick_stream(g, p);
+    QueryCtx c;
+    GEER_TRY(ensure_qstate(g, nq, &c.qs));
+    c.nq = nq;
+    c.lambda = g->lambda;
+    c.delta = p.delta;
+    c.tau = p.tau;
+    c.schedule = p.schedule;
+    c.seed = p.seed;
+    c.qid_offset = p.qid_offset;
+    GEER_TRY(g->ws.io.reserve((size_t)nq * sizeof(int32_t) + 256));
+    int32_t *d_fixed = g->ws.io.as<int32_t>();
+    GEER_HIP(hipMemcpyAsync(c.qs.s, d_s, nq * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    GEER_HIP(hipMemcpyAsync(c.qs.t, d_t, nq * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    GEER_HIP(hipMemcpyAsync(c.qs.eps, d_eps, nq * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (p.schedule == GEER_SCHEDULE_FIXED)
+        GEER_HIP(hipMemcpyAsync(d_fixed, p.fixed_ell_b, nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    std::vector<double> heps(nq);
+    GEER_HIP(hipMemcpyAsync(heps.data(), d_eps, nq * sizeof(double), hipMemcpyDeviceToHost, st));
+    GEER_HIP(hipStreamSynchronize(st));
+    double min_eps = 1e300;
+    for (double e : heps)
+        if (e > 0.0 && e < min_eps) min_eps = e;
+    GEER_TRY(run_queries(g, c, p, d_fixed, min_eps, st));
+    GEER_TRY(launch_finalize(g, c, d_r_out, d_stats, st));
+    GEER_HIP(hipStreamSynchronize(st));
+    // invalid entries were turned into NaN results by the init kernel
+    std::vector<int32_t> stop(nq);
+    GEER_HIP(hipMemcpy(stop.data(), c.qs.stop, nq * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < nq; ++i)
+        if (stop[i] < 0)
+            return fail(GEER_E_INVALID_ARG, "query " + std::to_string(i) + ": node id or eps invalid");
+    return GEER_OK;
+}
+
+geer_status geer_smm(geer_graph *g, int32_t nq, const int32_t *s, const int32_t *t, int32_t hops,
+                     uint32_t flags, int32_t col_tile, void *vec_out, double *rb_out,
+                     double *top2_out, int64_t *supp_out)
+{
+    if (!g) return fail(GEER_E_INVALID_ARG, "graph is NULL");
+    if (nq < 1 || nq > kMaxPairs) return fail(GEER_E_INVALID_ARG, "nq must be in 1..64");
+    if (!s || !t || !vec_out) return fail(GEER_E_INVALID_ARG, "NULL array");
+    if (hops < 0) return fail(GEER_E_INVALID_ARG, "hops must be >= 0");
+    if (col_tile != 0 && col_tile != 32 && col_tile != 64 && col_tile != 128)
+        return fail(GEER_E_INVALID_ARG, "col_tile must be 0, 32, 64 or 128");
+    for (int i = 0; i < nq; ++i)
+        if (s[i] < 0 || s[i] >= g->n || t[i] < 0 || t[i] >= g->n)
+            return fail(GEER_E_INVALID_ARG, "node out of range");
+    GEER_HIP(hipSetDevice(g->device));
+    hipStream_t st = g->stream;
+    const int vs = (flags & GEER_FLAG_FP64_VECTORS) ? 8 : 4;
+    QueryCtx c;
+    GEER_TRY(ensure_qstate(g, nq, &c.qs));
+    c.nq = nq;
+    c.lambda = 0.5;
+    c.delta = 0.01;
+    c.tau = 5;
+    c.schedule = GEER_SCHEDULE_FIXED;
+    c.seed = 0;
+    c.qid_offset = 0;
+    GEER_TRY(ensure_slots(g, std::max(1, g->ws.slots), vs));
+    std::vector<double> ones(nq, 1.0);
+    GEER_HIP(hipMemcpyAsync(c.qs.s, s, nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    GEER_HIP(hipMemcpyAsync(c.qs.t, t, nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    GEER_HIP(hipMemcpyAsync(c.qs.eps, ones.data(), nq * sizeof(double), hipMemcpyHostToDevice, st));
+    GEER_TRY(launch_init_queries(g, c, nullptr, hops, st));
+    SlotView sv{g->ws.pool.as<char>(), g->ws.bits.as<uint32_t>(), (size_t)g->n, vs};
+    const int tile = col_tile ? col_tile : default_col_tile(g, vs);
+    int done = 0;
+    if (hops > 0) GEER_TRY(smm_batch(g, c, sv, 0, 0, nq, tile, hops, st, &done));
+    GEER_HIP(hipStreamSynchronize(st));
+    const size_t n = (size_t)g->n;
+    if (hops == 0) {
+        // the hop-0 vectors are e_s and e_t
+        std::memset(vec_out, 0, n * 2 * nq * vs);
+        for (int j = 0; j < nq; ++j) {
+            if (vs == 4) {
+                ((float *)vec_out)[(size_t)s[j] * 2 * nq + 2 * j] = 1.0f;
+                ((float *)vec_out)[(size_t)t[j] * 2 * nq + 2 * j + 1] = 1.0f;
+            } else {
+                ((double *)vec_out)[(size_t)s[j] * 2 * nq + 2 * j] = 1.0;
+                ((double *)vec_out)[(size_t)t[j] * 2 * nq + 2 * j + 1] = 1.0;
+            }
+        }
+    } else {
+        const int which = hops == 1 ? 0 : (hops % 2 == 0 ? 1 : 2);
+        GEER_HIP(hipMemcpy2D(vec_out, (size_t)2 * nq * vs, sv.buf(0, which), (size_t)kCols * vs,
+                             (size_t)2 * nq * vs, n, hipMemcpyDeviceToHost));
+    }
+    if (rb_out) {
+        std::vector<double> rb(nq);
+        GEER_HIP(hipMemcpy(rb.data(), c.qs.rb, nq * sizeof(double), hipMemcpyDeviceToHost));
+        for (int j = 0; j < nq; ++j) rb_out[j] = s[j] == t[j] ? 0.0 : rb[j];
+    }
+    if (top2_out || supp_out) {
+        std::vector<double> cs(2 * kCols);
+        std::vector<int64_t> sd(kCols);
+        if (hops > 0) {
+            GEER_HIP(hipMemcpy(cs.data(), g->ws.colstat.ptr, 2 * kCols * sizeof(double), hipMemcpyDeviceToHost));
+            GEER_HIP(hipMemcpy(sd.data(), (char *)g->ws.colstat.ptr + 2 * kCols * sizeof(double),
+                               kCols * sizeof(int64_t), hipMemcpyDeviceToHost));
+        }
+        for (int j = 0; j < nq; ++j) {
+            for (int side = 0; side < 2; ++side) {
+                const int c2 = 2 * j + side;
+                double m1 = 1.0, m2 = 0.0;
+                int64_t d = 0;
+                if (hops > 0) {
+                    m1 = cs[c2];
+                    m2 = cs[kCols + c2];
+                    d = sd[c2];
+                } else {
+                    int32_t u = side ? t[j] : s[j];
+                    int32_t rp[2];
+                    GEER_HIP(hipMemcpy(rp, g->d_row_ptr + u, 2 * sizeof(int32_t), hipMemcpyDeviceToHost));
+                    d = rp[1] - rp[0];
+                }
+                if (top2_out) {
+                    top2_out[4 * j + 2 * side] = m1;
+                    top2_out[4 * j + 2 * side + 1] = m2;
+                }
+                if (supp_out) supp_out[2 * j + side] = d;
+            }
+        }
+    }
+    // restore H1 to zero
+    if (hops > 0) {
+        GEER_TRY(launch_hop1(g, c, 0, nq, sv.buf(0, 0), sv.bw(0, 0), nullptr, vs, true, st));
+        GEER_HIP(hipStreamSynchronize(st));
+    }
+    return GEER_OK;
+}
+
+geer_status geer_walk_traces(geer_graph *g, int32_t nw, const int32_t *start, const uint32_t *q,
+                             const uint32_t *batch, const uint32_t *k, const uint32_t *side,
+                             int32_t lf, uint64_t seed, int32_t *trace_out)
+{
+    if (!g) return fail(GEER_E_INVALID_ARG, "graph is NULL");
+    if (nw < 0 || lf < 0) return fail(GEER_E_INVALID_ARG, "negative size");
+    if (nw == 0 || lf == 0) return GEER_OK;
+    if (!start || !q || !batch || !k || !side || !trace_out)
+        return fail(GEER_E_INVALID_ARG, "NULL array");
+    for (int32_t i = 0; i < nw; ++i) {
+        if (start[i] < 0 || start[i] >= g->n) return fail(GEER_E_INVALID_ARG, "start out of range");
+        if (side[i] > 1) return fail(GEER_E_INVALID_ARG, "side must be 0 or 1");
+        if (batch[i] >= (1u << 31)) return fail(GEER_E_INVALID_ARG, "batch too large");
+    }
+    GEER_HIP(hipSetDevice(g->device));
+    hipStream_t st = g->stream;
+    const size_t bytes = (size_t)nw * (sizeof(int32_t) + 4 * sizeof(uint32_t)) + (size_t)nw * lf * sizeof(int32_t) + 256;
+    GEER_TRY(g->ws.io.reserve(bytes));
+    int32_t *d_start = g->ws.io.as<int32_t>();
+    uint32_t *d_q = reinterpret_cast<uint32_t *>(d_start + nw);
+    uint32_t *d_b = d_q + nw;
+    uint32_t *d_k = d_b + nw;
+    uint32_t *d_side = d_k + nw;
+    int32_t *d_trace = reinterpret_cast<int32_t *>(d_side + nw);
+    GEER_HIP(hipMemcpyAsync(d_start, start, nw * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    GEER_HIP(hipMemcpyAsync(d_q, q, nw * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    GEER_HIP(hipMemcpyAsync(d_b, batch, nw * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    GEER_HIP(hipMemcpyAsync(d_k, k, nw * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    GEER_HIP(hipMemcpyAsync(d_side, side, nw * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    GEER_TRY(launch_walk_traces(g, nw, d_start, d_q, d_b, d_k, d_side, lf, seed, d_trace, st));
+    GEER_HIP(hipMemcpyAsync(trace_out, d_trace, (size_t)nw * lf * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GEER_HIP(hipStreamSynchronize(st));
+    return GEER_OK;
+}
+
+}  // extern "C"
+
+namespace geer {
+
+__global__ void k_amc_setup(QState qs, const int32_t *__restrict__ row_ptr, int32_t lf,
+                            double eps, int32_t tau, double delta, int64_t voff,
+                            const double *__restrict__ cs_m1, const double *__restrict__ cs_m2)
+{
+    const double ids = 1.0 / (row_ptr[qs.s[0] + 1] - row_ptr[qs.s[0]]);
+    const double idt = 1.0 / (row_ptr[qs.t[0] + 1] - row_ptr[qs.t[0]]);
+    qs.eps[0] = eps;
+    qs.ell[0] = -1;
+    qs.lb[0] = -1;
+    qs.lf[0] = lf;
+    qs.vec_off[0] = voff;
+    qs.batches[0] = 0;
+    qs.walk_pairs[0] = 0;
+    qs.rb[0] = 0.0;
+    qs.rf[0] = 0.0;
+    qs.zsum[0] = qs.z2sum[0] = qs.var[0] = qs.f[0] = 0.0;
+    qs.supp_sum[0] = 0;
+    qs.fallback[0] = 0;
+    qs.tau_q[0] = tau;
+    double psi = lf > 0 ? psi_of(lf, cs_m1[0], cs_m2[0], cs_m1[1], cs_m2[1], ids, idt) : 0.0;
+    double es = lf > 0 ? eta_star_of(psi, eps, tau, delta) : 0.0;
+    qs.psi[0] = psi;
+    qs.eta_star[0] = es;
+    qs.eta1[0] = lf > 0 ? eta1_of(es, tau) : 0;
+    qs.active_amc[0] = qs.eta1[0] > 0 ? 1 : 0;
+    qs.stop[0] = qs.active_amc[0] ? GEER_STOP_CAP : GEER_STOP_NO_WALKS;
+}
+
+}  // namespace geer
+
+extern "C" geer_status geer_amc(geer_graph *g, int32_t s, int32_t t, const double *x,
+                                const double *y, double eps, int32_t lf, int32_t tau,
+                                double delta, uint64_t seed, uint32_t q, uint32_t flags,
+                                double *rf_out, geer_query_stats *stats)
+{
+    if (!g) return fail(GEER_E_INVALID_ARG, "graph is NULL");
+    if (!x || !y || !rf_out) return fail(GEER_E_INVALID_ARG, "NULL array");
+    if (s < 0 || s >= g->n || t < 0 || t >= g->n) return fail(GEER_E_INVALID_ARG, "node out of range");
+    if (!(eps > 0.0) || std::isinf(eps)) return fail(GEER_E_INVALID_ARG, "eps must be > 0");
+    if (lf < 0) return fail(GEER_E_INVALID_ARG, "lf must be >= 0");
+    if (tau < 1 || tau > 30) return fail(GEER_E_INVALID_ARG, "tau must be in 1..30");
+    if (!(delta > 0.0 && delta < 1.0)) return fail(GEER_E_INVALID_ARG, "delta must be in (0,1)");
+    const int32_t n = g->n;
+    for (int32_t v = 0; v < n; ++v)
+        if (!(x[v] >= 0.0) || !(y[v] >= 0.0) || std::isinf(x[v]) || std::isinf(y[v]))
+            return fail(GEER_E_INVALID_ARG, "vectors must be finite and non-negative");
+    GEER_HIP(hipSetDevice(g->device));
+    hipStream_t st = g->stream;
+    const int vs = (flags & GEER_FLAG_FP64_VECTORS) ? 8 : 4;
+    QueryCtx c;
+    GEER_TRY(ensure_qstate(g, 1, &c.qs));
+    c.nq = 1;
+    c.lambda = 0.5;
+    c.delta = delta;
+    c.tau = tau;
+    c.schedule = GEER_SCHEDULE_FIXED;
+    c.seed = seed;
+    c.qid_offset = (int64_t)q;
+    GEER_TRY(ensure_slots(g, std::max(1, g->ws.slots), vs));
+    SlotView sv{g->ws.pool.as<char>(), g->ws.bits.as<uint32_t>(), (size_t)n, vs};
+    // interleave (x, y) into columns 0, 1 of slot 0's A buffer
+    std::vector<char> host((size_t)n * 2 * vs);
+    for (int32_t v = 0; v < n; ++v) {
+        if (vs == 4) {
+            ((float *)host.data())[2 * (size_t)v] = (float)x[v];
+            ((float *)host.data())[2 * (size_t)v + 1] = (float)y[v];
+        } else {
+            ((double *)host.data())[2 * (size_t)v] = x[v];
+            ((double *)host.data())[2 * (size_t)v + 1] = y[v];
+        }
+    }
+    GEER_HIP(hipMemcpy2D(sv.buf(0, 1), (size_t)kCols * vs, host.data(), (size_t)2 * vs, (size_t)2 * vs,
+                         (size_t)n, hipMemcpyHostToDevice));
+    GEER_HIP(hipMemcpyAsync(c.qs.s, &s, sizeof(int32_t), hipMemcpyHostToDevice, st));
+    GEER_HIP(hipMemcpyAsync(c.qs.t, &t, sizeof(int32_t), hipMemcpyHostToDevice, st));
+    GEER_TRY(launch_column_top2(g, sv.buf(0, 1), 2, vs, st));
+    double *cs_m1 = g->ws.colstat.as<double>();
+    hipLaunchKernelGGL(k_amc_setup, dim3(1), dim3(1), 0, st, c.qs, g->d_row_ptr, lf, eps, tau, delta,
+                       sv.elem_off(0, 1), cs_m1, cs_m1 + kCols);
+    GEER_HIP(hipGetLastError());
+    AmcGroup grp;
+    grp.q0 = 0;
+    grp.nq = 1;
+    grp.pool = sv.pool;
+    grp.value_size = vs;
+    // the walk counter uses q + qid_offset with q = 0 here, so qid_offset = q
+    GEER_TRY(amc_phase(g, c, grp, st, 0));
+    GEER_TRY(g->ws.io.reserve(sizeof(double) + sizeof(geer_query_stats) + 64));
+    double *d_r = g->ws.io.as<double>();
+    geer_query_stats *d_st = reinterpret_cast<geer_query_stats *>((char *)g->ws.io.ptr + 16);
+    GEER_TRY(launch_finalize(g, c, d_r, d_st, st));
+    geer_query_stats hs;
+    GEER_HIP(hipMemcpyAsync(&hs, d_st, sizeof(hs), hipMemcpyDeviceToHost, st));
+    GEER_HIP(hipStreamSynchronize(st));
+    *rf_out = hs.r_f;
+    if (stats) {
+        *stats = hs;
+        stats->ell = -1;
+        stats->ell_b = -1;
+    }
+    return GEER_OK;
+}

@@ -1,0 +1,699 @@
+// SMM phase (Algorithm 2 inside Algorithm 3): repeated products with the
+// transition matrix P = D^-1 A for a batch of up to 64 pairs at once.
+//
+// Vectors of a batch live in an n x 128 row-major buffer: column 2j is s*_j,
+// column 2j+1 is t*_j, so one pair's two values at a node are adjacent (the
+// walk kernel later reads them with one 8-byte load).
+//
+//   hop 1:  exact sparse scatter.  (P e_u)(v) = 1/d(v) for v in N(u), 0 else.
+//   hop>=2: dense pull SpMM  y(v) = (1/d(v)) sum_{u in N(v)} x(u)  over a
+//           column tile.  A wavefront owns a row (degree <= 256) or a
+//           256-entry segment of a heavy row; lanes own column pairs; the
+//           neighbour rows are gathered with 8/16-byte loads.  Heavy-row
+//           segments are summed in a second pass in fixed order, so every
+//           result is deterministic (no floating-point atomics).
+//   Fused into the same pass: the structural support bitmask (OR over
+//   neighbours), per-column largest/second-largest value and the degree sum
+//   over the support, reduced per block and then per column.
+#include "geer_internal.h"
+
+namespace geer {
+
+template <class T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+
+template <class T> __device__ __forceinline__ void top2_push(T &m1, T &m2, T v)
+{
+    if (v > m1) {
+        m2 = m1;
+        m1 = v;
+    } else if (v > m2) {
+        m2 = v;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// init: per-query l (Eq. ell), r_b at hop 0, schedule targets
+// ----------------------------------------------------------------------------
+
+__global__ void k_init_queries(QState qs, int64_t nq, const int32_t *__restrict__ row_ptr,
+                               int32_t n, double lambda, double delta, int32_t tau,
+                               int32_t schedule, const int32_t *__restrict__ fixed,
+                               int32_t forced_hops)
+{
+    int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    int32_t s = qs.s[q], t = qs.t[q];
+    double eps = qs.eps[q];
+    qs.batches[q] = 0;
+    qs.walk_pairs[q] = 0;
+    qs.eta1[q] = 0;
+    qs.psi[q] = 0.0;
+    qs.eta_star[q] = 0.0;
+    qs.zsum[q] = qs.z2sum[q] = qs.var[q] = qs.f[q] = qs.rf[q] = 0.0;
+    qs.fallback[q] = 0;
+    qs.tau_q[q] = tau;
+    qs.vec_off[q] = -1;
+    qs.lb[q] = 0;
+    bool bad = s < 0 || s >= n || t < 0 || t >= n || !(eps > 0.0) || isinf(eps);
+    if (bad) {
+        qs.ell[q] = 0;
+        qs.lf[q] = 0;
+        qs.lb_target[q] = 0;
+        qs.rb[q] = 0.0;
+        qs.supp_sum[q] = 0;
+        qs.active_smm[q] = 0;
+        qs.active_amc[q] = 0;
+        qs.stop[q] = -1;
+        qs.r[q] = __builtin_nan("");
+        return;
+    }
+    if (s == t && forced_hops < 0) {  // r(s,s) = 0 (Section 2.2)
+        qs.ell[q] = 0;
+        qs.lf[q] = 0;
+        qs.lb_target[q] = 0;
+        qs.rb[q] = 0.0;
+        qs.supp_sum[q] = 0;
+        qs.active_smm[q] = 0;
+        qs.active_amc[q] = 0;
+        qs.stop[q] = GEER_STOP_SAME_NODE;
+        qs.r[q] = 0.0;
+        return;
+    }
+    int32_t ds = row_ptr[s + 1] - row_ptr[s], dt = row_ptr[t + 1] - row_ptr[t];
+    double ids = 1.0 / ds, idt = 1.0 / dt;
+    int32_t ell = forced_hops >= 0 ? forced_hops : ell_of(ds, dt, eps, lambda);
+    int32_t target = ell;
+    if (forced_hops < 0 && schedule == GEER_SCHEDULE_FIXED)
+        target = min(max(fixed[q], 0), ell);
+    qs.ell[q] = ell;
+    qs.lb_target[q] = target;
+    qs.rb[q] = ids + idt;  // hop-0 term: e_s(s)/d(s) + e_t(t)/d(t), cross terms 0 for s != t
+    qs.supp_sum[q] = (int64_t)ds + dt;
+    qs.r[q] = 0.0;
+    bool smm = ell > 0 && target > 0;
+    qs.active_smm[q] = smm ? 1 : 0;
+    if (!smm) {
+        // AMC straight from e_s, e_t: max1 = 1, max2 = 0 for both vectors
+        int32_t lf = ell;
+        qs.lf[q] = lf;
+        if (lf > 0) {
+            double psi = psi_of(lf, 1.0, 0.0, 1.0, 0.0, ids, idt);
+            double es = eta_star_of(psi, eps, tau, delta);
+            qs.psi[q] = psi;
+            qs.eta_star[q] = es;
+            qs.eta1[q] = eta1_of(es, tau);
+            qs.active_amc[q] = qs.eta1[q] > 0 ? 1 : 0;
+            qs.stop[q] = GEER_STOP_CAP;
+        } else {
+            qs.active_amc[q] = 0;
+            qs.stop[q] = GEER_STOP_NO_WALKS;
+        }
+    } else {
+        qs.lf[q] = ell;
+        qs.active_amc[q] = 0;
+        qs.stop[q] = GEER_STOP_NO_WALKS;
+    }
+}
+
+geer_status launch_init_queries(geer_graph *g, const QueryCtx &c, const int32_t *d_fixed,
+                                int32_t forced_hops, hipStream_t st)
+{
+    if (c.nq == 0) return GEER_OK;
+    int blocks = (int)((c.nq + 255) / 256);
+    hipLaunchKernelGGL(k_init_queries, dim3(blocks), dim3(256), 0, st, c.qs, c.nq, g->d_row_ptr,
+                       g->n, c.lambda, c.delta, c.tau, c.schedule, d_fixed, forced_hops);
+    GEER_HIP(hipGetLastError());
+    return GEER_OK;
+}
+
+// ----------------------------------------------------------------------------
+// hop 1: sparse scatter of P e_u into the (all-zero) H1 buffer; with
+// `clear` the same positions are reset to zero instead.
+// One wavefront per column (pair j, side).
+// ----------------------------------------------------------------------------
+
+template <class T>
+__global__ __launch_bounds__(64) void k_hop1(QState qs, int64_t q0,
+                                             const int32_t *__restrict__ row_ptr,
+                                             const int32_t *__restrict__ col_idx,
+                                             const T *__restrict__ inv_deg, T *__restrict__ h1,
+                                             uint32_t *__restrict__ h1_bits, int clear,
+                                             double *__restrict__ cs_m1, double *__restrict__ cs_m2,
+                                             int64_t *__restrict__ cs_sd)
+{
+    const int c = blockIdx.x;  // column within the batch
+    const int j = c >> 1, side = c & 1;
+    const int64_t q = q0 + j;
+    const int lane = threadIdx.x;
+    if (!clear && !qs.active_smm[q]) return;
+    if (clear && qs.lb[q] < 1) return;  // hop 1 never ran for this pair
+    const int32_t u = side ? qs.t[q] : qs.s[q];
+    const int32_t b = row_ptr[u], e = row_ptr[u + 1];
+    const uint32_t bit = 1u << (c & 31);
+    T m1 = 0, m2 = 0;
+    int64_t sd = 0;
+    for (int32_t k = b + lane; k < e; k += 64) {
+        int32_t v = col_idx[k];
+        T val = inv_deg[v];
+        size_t off = (size_t)v * kCols + c;
+        uint32_t *bw = h1_bits + (size_t)v * kBitWords + (c >> 5);
+        if (clear) {
+            h1[off] = T(0);
+            atomicAnd(bw, ~bit);
+        } else {
+            h1[off] = val;
+            atomicOr(bw, bit);
+            top2_push(m1, m2, val);
+            sd += row_ptr[v + 1] - row_ptr[v];
+        }
+    }
+    if (clear) return;
+    // wavefront reduction of (max1, max2, degree sum)
+    for (int o = 32; o > 0; o >>= 1) {
+        T o1 = __shfl_xor(m1, o), o2 = __shfl_xor(m2, o);
+        int64_t osd = __shfl_xor(sd, o);
+        top2_push(m1, m2, o1);
+        top2_push(m1, m2, o2);
+        sd += osd;
+    }
+    if (lane == 0) {
+        cs_m1[c] = (double)m1;
+        cs_m2[c] = (double)m2;  // the zero entries (e.g. u itself) make max2 >= 0 exact
+        cs_sd[c] = sd;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// dense hop: gather over a range of CSR entries into per-lane accumulators
+// ----------------------------------------------------------------------------
+
+template <class T, int KT>
+__device__ __forceinline__ void gather_range(const int32_t *__restrict__ col_idx,
+                                             const T *__restrict__ in,
+                                             const uint32_t *__restrict__ in_bits, int32_t b,
+                                             int32_t e, int lane, int slot, int col, int bw,
+                                             typename Vec2<T>::type &acc, uint32_t &bacc)
+{
+    using T2 = typename Vec2<T>::type;
+    constexpr int LPR = KT / 2;
+    constexpr int NS = 64 / LPR;
+    constexpr int U = 8;
+    // Every lane runs the same trip counts so that the index broadcasts
+    // (cross-lane reads) always execute with the whole wavefront active.
+    for (int32_t base = b; base < e; base += 64) {
+        const int cnt = min(64, e - base);
+        const int32_t myidx = lane < cnt ? col_idx[base + lane] : 0;
+        for (int k0 = 0; k0 < cnt; k0 += U * NS) {
+            int32_t u[U];
+            bool ok[U];
+#pragma unroll
+            for (int i = 0; i < U; ++i) {
+                const int kk = k0 + i * NS + slot;
+                ok[i] = kk < cnt;
+                u[i] = __shfl(myidx, ok[i] ? kk : 0);
+            }
+            T2 x[U];
+            uint32_t w[U];
+#pragma unroll
+            for (int i = 0; i < U; ++i) {
+                if (ok[i]) {
+                    x[i] = *reinterpret_cast<const T2 *>(in + (size_t)u[i] * kCols + col);
+                    w[i] = in_bits[(size_t)u[i] * kBitWords + bw];
+                } else {
+                    x[i].x = T(0);
+                    x[i].y = T(0);
+                    w[i] = 0u;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < U; ++i) {
+                acc.x += x[i].x;
+                acc.y += x[i].y;
+                bacc |= w[i];
+            }
+        }
+    }
+}
+
+// Reduce accumulators of the NS neighbour slots into slot 0.
+template <class T, int KT>
+__device__ __forceinline__ void reduce_slots(typename Vec2<T>::type &acc, uint32_t &bacc)
+{
+    constexpr int LPR = KT / 2;
+#pragma unroll
+    for (int o = LPR; o < 64; o <<= 1) {
+        acc.x += __shfl_xor(acc.x, o);
+        acc.y += __shfl_xor(acc.y, o);
+        bacc |= __shfl_xor(bacc, o);
+    }
+}
+
+// Write one finished row: values (active pairs only; a stopped pair's vectors
+// may live in this buffer), the support word, and the per-lane statistics.
+template <class T, int KT>
+__device__ __forceinline__ void emit_row(T *__restrict__ out, uint32_t *__restrict__ out_bits,
+                                         int32_t v, int32_t deg, T idg,
+                                         const typename Vec2<T>::type &acc, uint32_t bacc,
+                                         int lane, int slot, int col, int bw, bool act, T &m1s,
+                                         T &m2s, T &m1t, T &m2t, uint32_t &sds, uint32_t &sdt)
+{
+    using T2 = typename Vec2<T>::type;
+    const int bsh = col & 31;
+    uint32_t mine = act ? ((bacc >> bsh) & 3u) : 0u;
+    uint32_t word = mine << bsh;
+    // OR the 16 lanes that share this support word (32 columns)
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) word |= __shfl_xor(word, o);
+    if (slot == 0) {
+        T2 y;
+        y.x = acc.x * idg;
+        y.y = acc.y * idg;
+        if (act) {
+            *reinterpret_cast<T2 *>(out + (size_t)v * kCols + col) = y;
+            top2_push(m1s, m2s, y.x);
+            top2_push(m1t, m2t, y.y);
+            if (mine & 1u) sds += (uint32_t)deg;
+            if (mine & 2u) sdt += (uint32_t)deg;
+        }
+        if ((lane & 15) == 0) out_bits[(size_t)v * kBitWords + bw] = word;
+    }
+}
+
+// Per-block reduction of the lane statistics, written to the partials at row `prow`.
+template <class T, int KT>
+__device__ __forceinline__ void write_block_stats(int lane, int wave, int slot, int col, T m1s,
+                                                  T m2s, T m1t, T m2t, uint32_t sds,
+                                                  uint32_t sdt, size_t prow,
+                                                  double *__restrict__ p_m1,
+                                                  double *__restrict__ p_m2,
+                                                  int64_t *__restrict__ p_sd)
+{
+    constexpr int LPR = KT / 2;
+    constexpr int NW = 4;
+    __shared__ T s_m1[NW][KT], s_m2[NW][KT];
+    __shared__ uint32_t s_sd[NW][KT];
+    if (slot == 0) {
+        const int cl = lane % LPR;
+        s_m1[wave][2 * cl] = m1s;
+        s_m2[wave][2 * cl] = m2s;
+        s_m1[wave][2 * cl + 1] = m1t;
+        s_m2[wave][2 * cl + 1] = m2t;
+        s_sd[wave][2 * cl] = sds;
+        s_sd[wave][2 * cl + 1] = sdt;
+    }
+    __syncthreads();
+    const int col0 = col - 2 * (lane % LPR);
+    for (int c = threadIdx.x; c < KT; c += blockDim.x) {
+        T a1 = s_m1[0][c], a2 = s_m2[0][c];
+        int64_t sd = s_sd[0][c];
+        for (int w = 1; w < NW; ++w) {
+            top2_push(a1, a2, s_m1[w][c]);
+            top2_push(a1, a2, s_m2[w][c]);
+            sd += s_sd[w][c];
+        }
+        size_t o = prow * kCols + col0 + c;
+        p_m1[o] = (double)a1;
+        p_m2[o] = (double)a2;
+        p_sd[o] = sd;
+    }
+}
+
+template <class T, int KT>
+__global__ __launch_bounds__(256) void k_hop_light(
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
+    const T *__restrict__ inv_deg, const int32_t *__restrict__ rows, int32_t nrows,
+    const T *__restrict__ in, T *__restrict__ out, const uint32_t *__restrict__ in_bits,
+    uint32_t *__restrict__ out_bits, const uint64_t *__restrict__ mask_p, int col0,
+    double *__restrict__ p_m1, double *__restrict__ p_m2, int64_t *__restrict__ p_sd)
+{
+    using T2 = typename Vec2<T>::type;
+    constexpr int LPR = KT / 2;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int slot = lane / LPR;
+    const int col = col0 + 2 * (lane % LPR);
+    const int bw = col >> 5;
+    const bool act = ((*mask_p) >> (col >> 1)) & 1ull;
+    T m1s = 0, m2s = 0, m1t = 0, m2t = 0;
+    uint32_t sds = 0, sdt = 0;
+    for (int32_t r = blockIdx.x * 4 + wave; r < nrows; r += gridDim.x * 4) {
+        const int32_t v = rows[r];
+        const int32_t b = row_ptr[v], e = row_ptr[v + 1];
+        T2 acc;
+        acc.x = T(0);
+        acc.y = T(0);
+        uint32_t bacc = 0;
+        gather_range<T, KT>(col_idx, in, in_bits, b, e, lane, slot, col, bw, acc, bacc);
+        reduce_slots<T, KT>(acc, bacc);
+        emit_row<T, KT>(out, out_bits, v, e - b, inv_deg[v], acc, bacc, lane, slot, col, bw, act,
+                        m1s, m2s, m1t, m2t, sds, sdt);
+    }
+    write_block_stats<T, KT>(lane, wave, slot, col, m1s, m2s, m1t, m2t, sds, sdt, blockIdx.x,
+                             p_m1, p_m2, p_sd);
+}
+
+// Heavy rows, pass 1: partial sums of 256-entry segments.
+template <class T, int KT>
+__global__ __launch_bounds__(256) void k_hop_segments(
+    const int32_t *__restrict__ col_idx, const int32_t *__restrict__ seg_b,
+    const int32_t *__restrict__ seg_e, int32_t nseg, const T *__restrict__ in,
+    const uint32_t *__restrict__ in_bits, T *__restrict__ segbuf, uint32_t *__restrict__ segbits,
+    int col0)
+{
+    using T2 = typename Vec2<T>::type;
+    constexpr int LPR = KT / 2;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int slot = lane / LPR;
+    const int col = col0 + 2 * (lane % LPR);
+    const int bw = col >> 5;
+    for (int32_t sgi = blockIdx.x * 4 + wave; sgi < nseg; sgi += gridDim.x * 4) {
+        T2 acc;
+        acc.x = T(0);
+        acc.y = T(0);
+        uint32_t bacc = 0;
+        gather_range<T, KT>(col_idx, in, in_bits, seg_b[sgi], seg_e[sgi], lane, slot, col, bw,
+                            acc, bacc);
+        reduce_slots<T, KT>(acc, bacc);
+        if (slot == 0) {
+            *reinterpret_cast<T2 *>(segbuf + (size_t)sgi * kCols + col) = acc;
+            if ((lane & 15) == 0) segbits[(size_t)sgi * kBitWords + bw] = bacc;
+        }
+    }
+}
+
+// Heavy rows, pass 2: sum the segments of each row in order, then emit.
+template <class T, int KT>
+__global__ __launch_bounds__(256) void k_hop_heavy_fin(
+    const int32_t *__restrict__ row_ptr, const T *__restrict__ inv_deg,
+    const int32_t *__restrict__ heavy_rows, const int32_t *__restrict__ seg_start, int32_t nheavy,
+    const T *__restrict__ segbuf, const uint32_t *__restrict__ segbits, T *__restrict__ out,
+    uint32_t *__restrict__ out_bits, const uint64_t *__restrict__ mask_p, int col0,
+    size_t prow0, double *__restrict__ p_m1, double *__restrict__ p_m2,
+    int64_t *__restrict__ p_sd)
+{
+    using T2 = typename Vec2<T>::type;
+    constexpr int LPR = KT / 2;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int slot = lane / LPR;
+    const int col = col0 + 2 * (lane % LPR);
+    const int bw = col >> 5;
+    const bool act = ((*mask_p) >> (col >> 1)) & 1ull;
+    T m1s = 0, m2s = 0, m1t = 0, m2t = 0;
+    uint32_t sds = 0, sdt = 0;
+    for (int32_t h = blockIdx.x * 4 + wave; h < nheavy; h += gridDim.x * 4) {
+        const int32_t v = heavy_rows[h];
+        T2 acc;
+        acc.x = T(0);
+        acc.y = T(0);
+        uint32_t bacc = 0;
+        if (slot == 0) {
+            for (int32_t sg = seg_start[h]; sg < seg_start[h + 1]; ++sg) {
+                T2 x = *reinterpret_cast<const T2 *>(segbuf + (size_t)sg * kCols + col);
+                acc.x += x.x;
+                acc.y += x.y;
+                bacc |= segbits[(size_t)sg * kBitWords + bw];
+            }
+        }
+        emit_row<T, KT>(out, out_bits, v, row_ptr[v + 1] - row_ptr[v], inv_deg[v], acc, bacc,
+                        lane, slot, col, bw, act, m1s, m2s, m1t, m2t, sds, sdt);
+    }
+    write_block_stats<T, KT>(lane, wave, slot, col, m1s, m2s, m1t, m2t, sds, sdt,
+                             prow0 + blockIdx.x, p_m1, p_m2, p_sd);
+}
+
+// Column statistics: reduce the per-block partials of every active column.
+__global__ __launch_bounds__(256) void k_colstat_reduce(const double *__restrict__ p_m1,
+                                                        const double *__restrict__ p_m2,
+                                                        const int64_t *__restrict__ p_sd,
+                                                        int nrows_part,
+                                                        const uint64_t *__restrict__ mask_p,
+                                                        double *__restrict__ cs_m1,
+                                                        double *__restrict__ cs_m2,
+                                                        int64_t *__restrict__ cs_sd)
+{
+    const int c = blockIdx.x;
+    if (!(((*mask_p) >> (c >> 1)) & 1ull)) return;
+    double a1 = 0.0, a2 = 0.0;
+    int64_t sd = 0;
+    for (int r = threadIdx.x; r < nrows_part; r += blockDim.x) {
+        size_t o = (size_t)r * kCols + c;
+        top2_push(a1, a2, p_m1[o]);
+        top2_push(a1, a2, p_m2[o]);
+        sd += p_sd[o];
+    }
+    __shared__ double s1[256], s2[256];
+    __shared__ int64_t ss[256];
+    s1[threadIdx.x] = a1;
+    s2[threadIdx.x] = a2;
+    ss[threadIdx.x] = sd;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            double b1 = s1[threadIdx.x], b2 = s2[threadIdx.x];
+            top2_push(b1, b2, s1[threadIdx.x + w]);
+            top2_push(b1, b2, s2[threadIdx.x + w]);
+            s1[threadIdx.x] = b1;
+            s2[threadIdx.x] = b2;
+            ss[threadIdx.x] += ss[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        cs_m1[c] = s1[0];
+        cs_m2[c] = s2[0];
+        cs_sd[c] = ss[0];
+    }
+}
+
+int grid_blocks_dense(const geer_graph *g) { return std::max(1, g->num_cus * 8); }
+
+static int heavy_fin_blocks(const geer_graph *g)
+{
+    return std::max(1, std::min(g->num_cus * 2, (g->n_heavy + 3) / 4));
+}
+
+template <class T, int KT>
+static geer_status hop_dense_t(geer_graph *g, const HopArgs &a, hipStream_t st)
+{
+    Workspace &ws = g->ws;
+    const int nb = grid_blocks_dense(g);
+    const int nf = heavy_fin_blocks(g);
+    const size_t prows = (size_t)nb + nf;
+    double *p_m1 = ws.part.as<double>();
+    double *p_m2 = p_m1 + prows * kCols;
+    int64_t *p_sd = reinterpret_cast<int64_t *>(p_m2 + prows * kCols);
+    const T *inv = std::is_same<T, float>::value ? (const T *)g->d_inv_deg_f
+                                                 : (const T *)g->d_inv_deg_d;
+    const T *in = (const T *)a.in;
+    T *out = (T *)a.out;
+    if (g->n_seg > 0) {
+        T *segbuf = ws.segbuf.as<T>();
+        uint32_t *segbits = reinterpret_cast<uint32_t *>(segbuf + (size_t)g->n_seg * kCols);
+        int sb = std::max(1, std::min(nb, (g->n_seg + 3) / 4));
+        hipLaunchKernelGGL((k_hop_segments<T, KT>), dim3(sb), dim3(256), 0, st, g->d_col_idx,
+                           g->d_seg_begin, g->d_seg_end, g->n_seg, in, a.in_bits, segbuf, segbits,
+                           a.col0);
+        GEER_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL((k_hop_light<T, KT>), dim3(nb), dim3(256), 0, st, g->d_row_ptr,
+                       g->d_col_idx, inv, g->d_light_rows, g->n_light, in, out, a.in_bits,
+                       a.out_bits, a.mask, a.col0, p_m1, p_m2, p_sd);
+    GEER_HIP(hipGetLastError());
+    if (g->n_heavy > 0) {
+        T *segbuf = ws.segbuf.as<T>();
+        uint32_t *segbits = reinterpret_cast<uint32_t *>(segbuf + (size_t)g->n_seg * kCols);
+        hipLaunchKernelGGL((k_hop_heavy_fin<T, KT>), dim3(nf), dim3(256), 0, st, g->d_row_ptr,
+                           inv, g->d_heavy_rows, g->d_heavy_seg_start, g->n_heavy, segbuf,
+                           segbits, out, a.out_bits, a.mask, a.col0, (size_t)nb, p_m1, p_m2,
+                           p_sd);
+        GEER_HIP(hipGetLastError());
+    } else {
+        // keep the partial rows of the (absent) heavy pass neutral
+        GEER_HIP(hipMemsetAsync(p_m1 + (size_t)nb * kCols, 0, (size_t)nf * kCols * sizeof(double), st));
+        GEER_HIP(hipMemsetAsync(p_m2 + (size_t)nb * kCols, 0, (size_t)nf * kCols * sizeof(double), st));
+        GEER_HIP(hipMemsetAsync(p_sd + (size_t)nb * kCols, 0, (size_t)nf * kCols * sizeof(int64_t), st));
+    }
+    return GEER_OK;
+}
+
+geer_status launch_hop_dense(geer_graph *g, const HopArgs &a, int value_size, hipStream_t st)
+{
+    Workspace &ws = g->ws;
+    const int nb = grid_blocks_dense(g);
+    const int nf = heavy_fin_blocks(g);
+    const size_t prows = (size_t)nb + nf;
+    GEER_TRY(ws.part.reserve(prows * kCols * (2 * sizeof(double) + sizeof(int64_t))));
+    GEER_TRY(ws.segbuf.reserve((size_t)std::max(g->n_seg, 1) *
+                               (kCols * (size_t)value_size + kBitWords * sizeof(uint32_t))));
+    const int kt = a.col_tile;
+    for (int c0 = 0; c0 < kCols; c0 += kt) {
+        HopArgs t = a;
+        t.col0 = c0;
+        geer_status s = GEER_E_INVALID_ARG;
+        if (value_size == 4) {
+            if (kt == 128) s = hop_dense_t<float, 128>(g, t, st);
+            else if (kt == 64) s = hop_dense_t<float, 64>(g, t, st);
+            else if (kt == 32) s = hop_dense_t<float, 32>(g, t, st);
+        } else {
+            if (kt == 128) s = hop_dense_t<double, 128>(g, t, st);
+            else if (kt == 64) s = hop_dense_t<double, 64>(g, t, st);
+            else if (kt == 32) s = hop_dense_t<double, 32>(g, t, st);
+        }
+        if (s != GEER_OK) return s == GEER_E_INVALID_ARG ? fail(s, "unsupported column tile") : s;
+    }
+    double *cs_m1 = ws.colstat.as<double>();
+    double *cs_m2 = cs_m1 + kCols;
+    int64_t *cs_sd = reinterpret_cast<int64_t *>(cs_m2 + kCols);
+    double *p_m1 = ws.part.as<double>();
+    double *p_m2 = p_m1 + prows * kCols;
+    int64_t *p_sd = reinterpret_cast<int64_t *>(p_m2 + prows * kCols);
+    hipLaunchKernelGGL(k_colstat_reduce, dim3(kCols), dim3(256), 0, st, p_m1, p_m2, p_sd,
+                       (int)prows, a.mask, cs_m1, cs_m2, cs_sd);
+    GEER_HIP(hipGetLastError());
+    return GEER_OK;
+}
+
+geer_status launch_hop1(geer_graph *g, const QueryCtx &c, int64_t q0, int nb, void *h1,
+                        uint32_t *h1_bits, const uint64_t *mask, int value_size, bool clear,
+                        hipStream_t st)
+{
+    (void)mask;
+    Workspace &ws = g->ws;
+    double *cs_m1 = ws.colstat.as<double>();
+    double *cs_m2 = cs_m1 + kCols;
+    int64_t *cs_sd = reinterpret_cast<int64_t *>(cs_m2 + kCols);
+    if (value_size == 4)
+        hipLaunchKernelGGL(k_hop1<float>, dim3(2 * nb), dim3(64), 0, st, c.qs, q0, g->d_row_ptr,
+                           g->d_col_idx, g->d_inv_deg_f, (float *)h1, h1_bits, clear ? 1 : 0,
+                           cs_m1, cs_m2, cs_sd);
+    else
+        hipLaunchKernelGGL(k_hop1<double>, dim3(2 * nb), dim3(64), 0, st, c.qs, q0, g->d_row_ptr,
+                           g->d_col_idx, g->d_inv_deg_d, (double *)h1, h1_bits, clear ? 1 : 0,
+                           cs_m1, cs_m2, cs_sd);
+    GEER_HIP(hipGetLastError());
+    return GEER_OK;
+}
+
+// ----------------------------------------------------------------------------
+// epilogue after a hop: r_b increment, switch rule, AMC parameters on stop
+// ----------------------------------------------------------------------------
+
+template <class T>
+__global__ void k_epilogue(QState qs, int64_t q0, int nb, int hop, const T *__restrict__ vec,
+                           int64_t vec_elem_off, const int32_t *__restrict__ row_ptr,
+                           const double *__restrict__ cs_m1, const double *__restrict__ cs_m2,
+                           const int64_t *__restrict__ cs_sd, uint64_t *__restrict__ mask,
+                           int32_t schedule, int32_t tau, double delta)
+{
+    const int j = threadIdx.x;
+    if (j >= nb) return;
+    const int64_t q = q0 + j;
+    if (!qs.active_smm[q]) return;
+    const int32_t s = qs.s[q], t = qs.t[q];
+    const double ids = 1.0 / (row_ptr[s + 1] - row_ptr[s]);
+    const double idt = 1.0 / (row_ptr[t + 1] - row_ptr[t]);
+    const size_t cs = 2 * j, ct = 2 * j + 1;
+    const double xs = (double)vec[(size_t)s * kCols + cs], xt = (double)vec[(size_t)t * kCols + cs];
+    const double ys = (double)vec[(size_t)s * kCols + ct], yt = (double)vec[(size_t)t * kCols + ct];
+    // Algorithm 2: r_b += s*(s)/d(s) + t*(t)/d(t) - s*(t)/d(s) - t*(s)/d(t)
+    const double rb = qs.rb[q] + (xs * ids + yt * idt - xt * ids - ys * idt);
+    qs.rb[q] = rb;
+    qs.lb[q] = hop;
+    const int32_t ell = qs.ell[q];
+    const int32_t lf = ell - hop;
+    const double eps = qs.eps[q];
+    const double psi = psi_of(lf, cs_m1[cs], cs_m2[cs], cs_m1[ct], cs_m2[ct], ids, idt);
+    const double es = eta_star_of(psi, eps, tau, delta);
+    const int64_t e1 = eta1_of(es, tau);
+    const int64_t sd = cs_sd[cs] + cs_sd[ct];
+    bool stop = hop >= qs.lb_target[q];
+    if (!stop && schedule == GEER_SCHEDULE_GREEDY) {
+        // Eq. (smm-amc): next-hop cost sum_{V_s} d + sum_{V_t} d versus h(l - l_b)
+        const double h = (ldexp(1.0, tau) - 1.0) * (double)e1;
+        stop = (double)sd > h;
+    }
+    if (stop) {
+        qs.active_smm[q] = 0;
+        qs.lf[q] = lf;
+        qs.supp_sum[q] = sd;
+        qs.vec_off[q] = vec_elem_off + 2 * j;
+        qs.psi[q] = lf > 0 ? psi : 0.0;
+        qs.eta_star[q] = lf > 0 ? es : 0.0;
+        qs.eta1[q] = lf > 0 ? e1 : 0;
+        qs.active_amc[q] = (lf > 0 && e1 > 0) ? 1 : 0;
+        qs.stop[q] = lf > 0 ? GEER_STOP_CAP : GEER_STOP_NO_WALKS;
+        atomicAnd(reinterpret_cast<unsigned long long *>(mask), ~(1ull << j));
+    }
+}
+
+geer_status launch_epilogue(geer_graph *g, const QueryCtx &c, int64_t q0, int nb, int hop,
+                            const void *vec, int64_t vec_elem_off, uint64_t *mask, int value_size,
+                            int dense, hipStream_t st)
+{
+    (void)dense;
+    Workspace &ws = g->ws;
+    double *cs_m1 = ws.colstat.as<double>();
+    double *cs_m2 = cs_m1 + kCols;
+    int64_t *cs_sd = reinterpret_cast<int64_t *>(cs_m2 + kCols);
+    if (value_size == 4)
+        hipLaunchKernelGGL(k_epilogue<float>, dim3(1), dim3(64), 0, st, c.qs, q0, nb, hop,
+                           (const float *)vec, vec_elem_off, g->d_row_ptr, cs_m1, cs_m2, cs_sd,
+                           mask, c.schedule, c.tau, c.delta);
+    else
+        hipLaunchKernelGGL(k_epilogue<double>, dim3(1), dim3(64), 0, st, c.qs, q0, nb, hop,
+                           (const double *)vec, vec_elem_off, g->d_row_ptr, cs_m1, cs_m2, cs_sd,
+                           mask, c.schedule, c.tau, c.delta);
+    GEER_HIP(hipGetLastError());
+    return GEER_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Largest / second-largest of the first `ncols` columns of a slot buffer
+// (used when AMC is given caller vectors).  One block per column.
+// ----------------------------------------------------------------------------
+
+template <class T>
+__global__ __launch_bounds__(256) void k_column_top2(const T *__restrict__ vec, int32_t n,
+                                                     double *__restrict__ cs_m1,
+                                                     double *__restrict__ cs_m2)
+{
+    const int c = blockIdx.x;
+    T a1 = 0, a2 = 0;
+    for (int32_t v = threadIdx.x; v < n; v += blockDim.x) top2_push(a1, a2, vec[(size_t)v * kCols + c]);
+    __shared__ double s1[256], s2[256];
+    s1[threadIdx.x] = (double)a1;
+    s2[threadIdx.x] = (double)a2;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            double b1 = s1[threadIdx.x], b2 = s2[threadIdx.x];
+            top2_push(b1, b2, s1[threadIdx.x + w]);
+            top2_push(b1, b2, s2[threadIdx.x + w]);
+            s1[threadIdx.x] = b1;
+            s2[threadIdx.x] = b2;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        cs_m1[c] = s1[0];
+        cs_m2[c] = s2[0];
+    }
+}
+
+geer_status launch_column_top2(geer_graph *g, const void *vec, int ncols, int value_size,
+                               hipStream_t st)
+{
+    double *cs_m1 = g->ws.colstat.as<double>();
+    double *cs_m2 = cs_m1 + kCols;
+    if (value_size == 4)
+        hipLaunchKernelGGL(k_column_top2<float>, dim3(ncols), dim3(256), 0, st,
+                           (const float *)vec, g->n, cs_m1, cs_m2);
+    else
+        hipLaunchKernelGGL(k_column_top2<double>, dim3(ncols), dim3(256), 0, st,
+                           (const double *)vec, g->n, cs_m1, cs_m2);
+    GEER_HIP(hipGetLastError());
+    return GEER_OK;
+}
+
+}  // namespace geer
