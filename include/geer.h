@@ -196,6 +196,27 @@ geer_status geer_amc(geer_graph *g, int32_t s, int32_t t, const double *x, const
                      double eps, int32_t lf, int32_t tau, double delta, uint64_t seed, uint32_t q,
                      uint32_t flags, double *rf_out, geer_query_stats *stats);
 
+/* ---- Kernel timing (HIP events on the stream each kernel runs on) ------- */
+
+/* One record per kernel kind: launches, summed event-timed duration, and
+ * the algorithmic bytes the launches had to move (SpMM hops: row offsets,
+ * column indices, the gathered vector rows once, the written rows once and
+ * the inverse degrees of the rows covered; walks: 20 bytes per step). */
+typedef struct geer_kernel_profile {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+    double alg_bytes;
+    double work_units;   /* SpMM: CSR entries x active columns; walks: steps */
+} geer_kernel_profile;
+
+/* Start (on != 0) or stop timing on this graph; starting clears the records. */
+geer_status geer_profile_enable(geer_graph *g, int32_t on);
+
+/* Copy up to cap records (waits for the timed work to finish). */
+geer_status geer_profile_read(geer_graph *g, geer_kernel_profile *out, int32_t cap,
+                              int32_t *count);
+
 /* Thread-local description of the last non-OK status on this thread. */
 const char *geer_last_error(void);
 

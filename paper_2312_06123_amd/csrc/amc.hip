@@ -23,9 +23,13 @@ template <> struct Val2<double> { using type = double2; };
 __global__ __launch_bounds__(1024) void k_amc_plan(QState qs, int64_t q0, int nq, int round,
                                                    int64_t *__restrict__ chunk_off,
                                                    int64_t *__restrict__ total,
-                                                   int32_t *__restrict__ overflow)
+                                                   int32_t *__restrict__ overflow,
+                                                   int64_t *__restrict__ steps)
 {
     __shared__ int64_t s_sum[1024];
+    __shared__ unsigned long long s_steps;
+    if (threadIdx.x == 0) s_steps = 0;
+    __syncthreads();
     const int tid = threadIdx.x;
     const int per = (nq + 1023) / 1024;
     const int a = min(nq, tid * per), b = min(nq, a + per);
@@ -36,6 +40,7 @@ __global__ __launch_bounds__(1024) void k_amc_plan(QState qs, int64_t q0, int nq
             int64_t eta = qs.eta1[q] << round;
             if (eta >= (int64_t(1) << 32)) *overflow = 1;
             local += (eta + kPairsPerChunk - 1) / kPairsPerChunk;
+            atomicAdd(&s_steps, (unsigned long long)(2 * eta * qs.lf[q]));
         }
     }
     s_sum[tid] = local;
@@ -59,6 +64,7 @@ __global__ __launch_bounds__(1024) void k_amc_plan(QState qs, int64_t q0, int nq
     if (tid == 1023) {
         chunk_off[nq] = s_sum[1023];
         *total = s_sum[1023];
+        *steps = (int64_t)s_steps;
     }
 }
 
@@ -193,14 +199,15 @@ geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hip
     int64_t *chunk_off = ws.chunk_off.as<int64_t>();
     int64_t *d_total = ws.misc.as<int64_t>() + 8;
     int32_t *d_over = reinterpret_cast<int32_t *>(ws.misc.as<int64_t>() + 9);
+    int64_t *d_steps = ws.misc.as<int64_t>() + 10;
     GEER_HIP(hipMemsetAsync(d_over, 0, sizeof(int32_t), st));
     const uint32_t key0 = (uint32_t)c.seed, key1 = (uint32_t)(c.seed >> 32);
     for (int round = 0; round < c.tau; ++round) {
         hipLaunchKernelGGL(k_amc_plan, dim3(1), dim3(1024), 0, st, c.qs, grp.q0, nq, round,
-                           chunk_off, d_total, d_over);
+                           chunk_off, d_total, d_over, d_steps);
         GEER_HIP(hipGetLastError());
-        int64_t host[2] = {0, 0};
-        GEER_HIP(hipMemcpyAsync(host, d_total, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        int64_t host[3] = {0, 0, 0};
+        GEER_HIP(hipMemcpyAsync(host, d_total, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
         GEER_HIP(hipStreamSynchronize(st));
         if (((int32_t *)&host[1])[0] != 0)
             return fail(GEER_E_INVALID_ARG, "AMC batch exceeds 2^32 walk pairs for a query");
@@ -209,6 +216,8 @@ geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hip
         GEER_TRY(ws.zpart.reserve((size_t)total * sizeof(double2)));
         const int64_t want_blocks = (total + 3) / 4;
         const int blocks = (int)std::min<int64_t>(want_blocks, (int64_t)g->num_cus * 16);
+        const double steps = (double)host[2];
+        int tok = prof_begin(g, st);
         if (grp.value_size == 4)
             hipLaunchKernelGGL(k_walk<float>, dim3(blocks), dim3(256), 0, st, c.qs, grp.q0, nq,
                                round, chunk_off, d_total, g->d_row_ptr, g->d_col_idx,
@@ -219,6 +228,8 @@ geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hip
                                round, chunk_off, d_total, g->d_row_ptr, g->d_col_idx,
                                (const double *)grp.pool, key0, key1, c.qid_offset,
                                ws.zpart.as<double2>());
+        // per step: row offsets of u (8 B), one column index (4 B), the pair's two values (8 B)
+        prof_end(g, tok, PK_WALK, 20.0 * steps, steps, st);
         GEER_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_amc_stop, dim3((nq + 3) / 4), dim3(256), 0, st, c.qs, grp.q0, nq,
                            round, chunk_off, ws.zpart.as<double2>(), c.tau, c.delta);

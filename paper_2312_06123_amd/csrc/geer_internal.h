@@ -81,6 +81,36 @@ struct Workspace {
     int64_t nq_cap = 0;
 };
 
+// Event timing of kernel launches (enabled by geer_profile_enable).
+enum ProfKind {
+    PK_HOP_LIGHT = 0,
+    PK_HOP_SEGMENTS,
+    PK_HOP_HEAVY_FIN,
+    PK_HOP1,
+    PK_COLSTAT,
+    PK_EPILOGUE,
+    PK_WALK,
+    PK_AMC_PLAN,
+    PK_AMC_STOP,
+    PK_FEATURES,
+    PK_MLP,
+    PK_COUNT
+};
+
+struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+    double bytes, units;
+};
+
+struct Profiler {
+    bool on = false;
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> spare;
+    int64_t launches[PK_COUNT] = {};
+    double ms[PK_COUNT] = {}, bytes[PK_COUNT] = {}, units[PK_COUNT] = {};
+};
+
 }  // namespace geer
 
 // ----------------------------------------------------------------------------
@@ -111,7 +141,9 @@ struct geer_graph {
     int32_t *d_seg_begin = nullptr;        // [n_seg] first CSR entry of each segment
     int32_t *d_seg_end = nullptr;          // [n_seg] one past the last entry
     int32_t n_seg = 0;
+    int64_t nnz_heavy = 0;                 // CSR entries in heavy rows
     geer::Workspace ws;
+    geer::Profiler prof;
 };
 
 // ----------------------------------------------------------------------------
@@ -202,6 +234,7 @@ struct HopArgs {
     const uint32_t *in_bits; // n x kBitWords
     uint32_t *out_bits;
     const uint64_t *mask;    // active pairs of the batch (bit j = pair j)
+    uint64_t host_mask;      // the same mask as seen by the host (for byte accounting)
     int col0, col_tile;      // column slice of this launch
 };
 
@@ -240,6 +273,10 @@ geer_status launch_finalize(geer_graph *g, const QueryCtx &c, double *d_r_out,
 geer_status launch_walk_traces(geer_graph *g, int32_t nw, const int32_t *start, const uint32_t *q,
                                const uint32_t *batch, const uint32_t *k, const uint32_t *side,
                                int32_t lf, uint64_t seed, int32_t *trace, hipStream_t st);
+
+// Profiling helpers (graph.hip): bracket a launch with events when enabled.
+int prof_begin(geer_graph *g, hipStream_t st);
+void prof_end(geer_graph *g, int token, int kind, double bytes, double units, hipStream_t st);
 
 // Workspace helpers (query.hip)
 geer_status ensure_qstate(geer_graph *g, int64_t nq, QState *qs);

@@ -2,6 +2,7 @@
 // degrees, and the SpMM work decomposition (light rows / heavy-row segments).
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <numeric>
 
 #include "geer_internal.h"
@@ -38,6 +39,60 @@ void DevBuf::release()
     if (ptr) (void)hipFree(ptr);
     ptr = nullptr;
     bytes = 0;
+}
+
+static hipEvent_t take_event(Profiler &p)
+{
+    if (!p.spare.empty()) {
+        hipEvent_t e = p.spare.back();
+        p.spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int prof_begin(geer_graph *g, hipStream_t st)
+{
+    Profiler &p = g->prof;
+    if (!p.on) return -1;
+    ProfRec r{};
+    r.a = take_event(p);
+    r.b = take_event(p);
+    if (!r.a || !r.b) return -1;
+    if (hipEventRecord(r.a, st) != hipSuccess) return -1;
+    p.recs.push_back(r);
+    return (int)p.recs.size() - 1;
+}
+
+void prof_end(geer_graph *g, int token, int kind, double bytes, double units, hipStream_t st)
+{
+    Profiler &p = g->prof;
+    if (!p.on || token < 0 || token >= (int)p.recs.size()) return;
+    ProfRec &r = p.recs[token];
+    r.kind = kind;
+    r.bytes = bytes;
+    r.units = units;
+    (void)hipEventRecord(r.b, st);
+}
+
+static geer_status prof_flush(geer_graph *g)
+{
+    Profiler &p = g->prof;
+    for (ProfRec &r : p.recs) {
+        GEER_HIP(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        GEER_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        p.launches[r.kind] += 1;
+        p.ms[r.kind] += ms;
+        p.bytes[r.kind] += r.bytes;
+        p.units[r.kind] += r.units;
+        p.spare.push_back(r.a);
+        p.spare.push_back(r.b);
+    }
+    p.recs.clear();
+    return GEER_OK;
 }
 
 }  // namespace geer
@@ -118,8 +173,12 @@ static geer_status build_graph(geer_graph *g, const int32_t *rp, const int32_t *
     std::vector<int32_t> light, heavy, seg_start, seg_b, seg_e;
     for (int32_t v = 0; v < n; ++v) {
         int32_t d = rp[v + 1] - rp[v];
-        if (d > kSegNnz) heavy.push_back(v);
-        else light.push_back(v);
+        if (d > kSegNnz) {
+            heavy.push_back(v);
+            g->nnz_heavy += d;
+        } else {
+            light.push_back(v);
+        }
     }
     std::stable_sort(light.begin(), light.end(), [&](int32_t a, int32_t b) {
         return rp[a + 1] - rp[a] > rp[b + 1] - rp[b];
@@ -199,8 +258,49 @@ void geer_graph_destroy(geer_graph *g)
                       &g->ws.colstat, &g->ws.qstate, &g->ws.chunk_off, &g->ws.zpart,
                       &g->ws.misc,  &g->ws.io};
     for (DevBuf *b : bufs) b->release();
+    for (ProfRec &r : g->prof.recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : g->prof.spare) (void)hipEventDestroy(e);
     if (g->stream) (void)hipStreamDestroy(g->stream);
     delete g;
+}
+
+geer_status geer_profile_enable(geer_graph *g, int32_t on)
+{
+    if (!g) return fail(GEER_E_INVALID_ARG, "graph is NULL");
+    GEER_TRY(prof_flush(g));
+    Profiler &p = g->prof;
+    p.on = on != 0;
+    if (p.on) {
+        for (int k = 0; k < PK_COUNT; ++k) {
+            p.launches[k] = 0;
+            p.ms[k] = p.bytes[k] = p.units[k] = 0.0;
+        }
+    }
+    return GEER_OK;
+}
+
+geer_status geer_profile_read(geer_graph *g, geer_kernel_profile *out, int32_t cap, int32_t *count)
+{
+    if (!g || (!out && cap > 0)) return fail(GEER_E_INVALID_ARG, "NULL argument");
+    GEER_TRY(prof_flush(g));
+    static const char *names[PK_COUNT] = {"hop_light", "hop_segments", "hop_heavy_fin", "hop1",
+                                          "colstat", "epilogue", "walk", "amc_plan", "amc_stop",
+                                          "features", "mlp"};
+    int32_t k = 0;
+    for (int i = 0; i < PK_COUNT && k < cap; ++i) {
+        geer_kernel_profile &r = out[k++];
+        std::memset(&r, 0, sizeof(r));
+        std::strncpy(r.name, names[i], sizeof(r.name) - 1);
+        r.launches = g->prof.launches[i];
+        r.total_ms = g->prof.ms[i];
+        r.alg_bytes = g->prof.bytes[i];
+        r.work_units = g->prof.units[i];
+    }
+    if (count) *count = k;
+    return GEER_OK;
 }
 
 geer_status geer_graph_set_lambda(geer_graph *g, double lambda)

@@ -139,6 +139,7 @@ static geer_status smm_batch(geer_graph *g, const QueryCtx &c, const SlotView &s
         a.in_bits = sv.bw(slot, win);
         a.out_bits = sv.bw(slot, wout);
         a.mask = d_mask;
+        a.host_mask = (uint64_t)m;
         a.col0 = 0;
         a.col_tile = col_tile;
         GEER_TRY(launch_hop_dense(g, a, sv.vs, st));

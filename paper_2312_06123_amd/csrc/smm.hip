@@ -487,26 +487,47 @@ static geer_status hop_dense_t(geer_graph *g, const HopArgs &a, hipStream_t st)
                                                  : (const T *)g->d_inv_deg_d;
     const T *in = (const T *)a.in;
     T *out = (T *)a.out;
+    // algorithmic bytes of this tile (split over the three kernels):
+    // 4(|R|+1) + 4 nnz(R) + b k |C| + b k |R| + 4 |R| with R = C = all rows and
+    // k = active columns of the tile; the gathered-vector term is shared in
+    // proportion to the CSR entries each kernel walks.
+    int kact = 0;
+    for (int j = a.col0 / 2; j < (a.col0 + KT) / 2; ++j) kact += (int)((a.host_mask >> j) & 1ull) * 2;
+    const double b = (double)sizeof(T), n = (double)g->n, nnz = (double)g->nnz;
+    const double nnz_h = (double)g->nnz_heavy, nnz_l = nnz - nnz_h;
+    const double xread = b * kact * n;
     if (g->n_seg > 0) {
         T *segbuf = ws.segbuf.as<T>();
         uint32_t *segbits = reinterpret_cast<uint32_t *>(segbuf + (size_t)g->n_seg * kCols);
         int sb = std::max(1, std::min(nb, (g->n_seg + 3) / 4));
+        int tok = prof_begin(g, st);
         hipLaunchKernelGGL((k_hop_segments<T, KT>), dim3(sb), dim3(256), 0, st, g->d_col_idx,
                            g->d_seg_begin, g->d_seg_end, g->n_seg, in, a.in_bits, segbuf, segbits,
                            a.col0);
+        prof_end(g, tok, PK_HOP_SEGMENTS, 4.0 * nnz_h + xread * (nnz_h / nnz), nnz_h * kact, st);
         GEER_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL((k_hop_light<T, KT>), dim3(nb), dim3(256), 0, st, g->d_row_ptr,
-                       g->d_col_idx, inv, g->d_light_rows, g->n_light, in, out, a.in_bits,
-                       a.out_bits, a.mask, a.col0, p_m1, p_m2, p_sd);
-    GEER_HIP(hipGetLastError());
+    {
+        const double nl = (double)g->n_light;
+        int tok = prof_begin(g, st);
+        hipLaunchKernelGGL((k_hop_light<T, KT>), dim3(nb), dim3(256), 0, st, g->d_row_ptr,
+                           g->d_col_idx, inv, g->d_light_rows, g->n_light, in, out, a.in_bits,
+                           a.out_bits, a.mask, a.col0, p_m1, p_m2, p_sd);
+        prof_end(g, tok, PK_HOP_LIGHT,
+                 4.0 * (nl + 1) + 4.0 * nnz_l + xread * (nnz_l / nnz) + b * kact * nl + 4.0 * nl,
+                 nnz_l * kact, st);
+        GEER_HIP(hipGetLastError());
+    }
     if (g->n_heavy > 0) {
         T *segbuf = ws.segbuf.as<T>();
         uint32_t *segbits = reinterpret_cast<uint32_t *>(segbuf + (size_t)g->n_seg * kCols);
+        const double nh = (double)g->n_heavy;
+        int tok = prof_begin(g, st);
         hipLaunchKernelGGL((k_hop_heavy_fin<T, KT>), dim3(nf), dim3(256), 0, st, g->d_row_ptr,
                            inv, g->d_heavy_rows, g->d_heavy_seg_start, g->n_heavy, segbuf,
                            segbits, out, a.out_bits, a.mask, a.col0, (size_t)nb, p_m1, p_m2,
                            p_sd);
+        prof_end(g, tok, PK_HOP_HEAVY_FIN, 4.0 * (nh + 1) + b * kact * nh + 4.0 * nh, 0.0, st);
         GEER_HIP(hipGetLastError());
     } else {
         // keep the partial rows of the (absent) heavy pass neutral
@@ -548,8 +569,10 @@ geer_status launch_hop_dense(geer_graph *g, const HopArgs &a, int value_size, hi
     double *p_m1 = ws.part.as<double>();
     double *p_m2 = p_m1 + prows * kCols;
     int64_t *p_sd = reinterpret_cast<int64_t *>(p_m2 + prows * kCols);
+    int tok = prof_begin(g, st);
     hipLaunchKernelGGL(k_colstat_reduce, dim3(kCols), dim3(256), 0, st, p_m1, p_m2, p_sd,
                        (int)prows, a.mask, cs_m1, cs_m2, cs_sd);
+    prof_end(g, tok, PK_COLSTAT, 0.0, 0.0, st);
     GEER_HIP(hipGetLastError());
     return GEER_OK;
 }
@@ -563,6 +586,7 @@ geer_status launch_hop1(geer_graph *g, const QueryCtx &c, int64_t q0, int nb, vo
     double *cs_m1 = ws.colstat.as<double>();
     double *cs_m2 = cs_m1 + kCols;
     int64_t *cs_sd = reinterpret_cast<int64_t *>(cs_m2 + kCols);
+    int tok = prof_begin(g, st);
     if (value_size == 4)
         hipLaunchKernelGGL(k_hop1<float>, dim3(2 * nb), dim3(64), 0, st, c.qs, q0, g->d_row_ptr,
                            g->d_col_idx, g->d_inv_deg_f, (float *)h1, h1_bits, clear ? 1 : 0,
@@ -571,6 +595,7 @@ geer_status launch_hop1(geer_graph *g, const QueryCtx &c, int64_t q0, int nb, vo
         hipLaunchKernelGGL(k_hop1<double>, dim3(2 * nb), dim3(64), 0, st, c.qs, q0, g->d_row_ptr,
                            g->d_col_idx, g->d_inv_deg_d, (double *)h1, h1_bits, clear ? 1 : 0,
                            cs_m1, cs_m2, cs_sd);
+    prof_end(g, tok, PK_HOP1, 0.0, 0.0, st);
     GEER_HIP(hipGetLastError());
     return GEER_OK;
 }
@@ -636,6 +661,7 @@ geer_status launch_epilogue(geer_graph *g, const QueryCtx &c, int64_t q0, int nb
     double *cs_m1 = ws.colstat.as<double>();
     double *cs_m2 = cs_m1 + kCols;
     int64_t *cs_sd = reinterpret_cast<int64_t *>(cs_m2 + kCols);
+    int tok = prof_begin(g, st);
     if (value_size == 4)
         hipLaunchKernelGGL(k_epilogue<float>, dim3(1), dim3(64), 0, st, c.qs, q0, nb, hop,
                            (const float *)vec, vec_elem_off, g->d_row_ptr, cs_m1, cs_m2, cs_sd,
@@ -644,6 +670,7 @@ geer_status launch_epilogue(geer_graph *g, const QueryCtx &c, int64_t q0, int nb
         hipLaunchKernelGGL(k_epilogue<double>, dim3(1), dim3(64), 0, st, c.qs, q0, nb, hop,
                            (const double *)vec, vec_elem_off, g->d_row_ptr, cs_m1, cs_m2, cs_sd,
                            mask, c.schedule, c.tau, c.delta);
+    prof_end(g, tok, PK_EPILOGUE, 0.0, 0.0, st);
     GEER_HIP(hipGetLastError());
     return GEER_OK;
 }

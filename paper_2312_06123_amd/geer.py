@@ -44,7 +44,7 @@ EXPORTED = [
     "geer_query_device", "geer_smm", "geer_walk_traces", "geer_amc", "geer_last_error",
     "geer_version", "geer_model_create", "geer_model_free", "geer_model_save", "geer_model_load",
     "geer_model_get_params", "geer_model_set_params", "geer_features", "geer_mlp_forward",
-    "geer_mlp_train_step", "geer_autotune",
+    "geer_mlp_train_step", "geer_autotune", "geer_profile_enable", "geer_profile_read",
 ]
 
 
@@ -82,6 +82,12 @@ class geer_query_stats(ctypes.Structure):
         ("psi", ctypes.c_double), ("eta_star", ctypes.c_double), ("sigma2", ctypes.c_double),
         ("f_last", ctypes.c_double),
     ]
+
+
+class geer_kernel_profile(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double), ("alg_bytes", ctypes.c_double),
+                ("work_units", ctypes.c_double)]
 
 
 STATS_DTYPE = np.dtype([(name, np.dtype(ctype)) for name, ctype in [
@@ -123,6 +129,8 @@ _SIGNATURES = {
     "geer_mlp_forward": ([_vp, _i64, _vp, _i32, _vp], _i32),
     "geer_mlp_train_step": ([_vp, _i64, _vp, _vp, _vp, _f64, _vp, _vp], _i32),
     "geer_autotune": ([_vp, _vp, _vp], _i32),
+    "geer_profile_enable": ([_vp, _i32], _i32),
+    "geer_profile_read": ([_vp, _vp, _i32, ctypes.POINTER(_i32)], _i32),
 }
 
 
@@ -295,6 +303,20 @@ def geer_amc(g, s: int, t: int, x, y, eps: float, lf: int, tau: int = 5, delta: 
                          float(delta), int(seed), int(q), GEER_FLAG_FP64_VECTORS if fp64 else 0,
                          ctypes.byref(rf), _ptr(st)))
     return rf.value, st[0]
+
+
+def geer_profile_enable(g, on: bool = True) -> None:
+    _check(_lib.geer_profile_enable(g, 1 if on else 0))
+
+
+def geer_profile_read(g) -> dict:
+    """{kernel name: {launches, total_ms, alg_bytes, work_units}}."""
+    recs = (geer_kernel_profile * 32)()
+    cnt = ctypes.c_int32()
+    _check(_lib.geer_profile_read(g, recs, 32, ctypes.byref(cnt)))
+    return {r.name.decode(): {"launches": r.launches, "total_ms": r.total_ms,
+                              "alg_bytes": r.alg_bytes, "work_units": r.work_units}
+            for r in recs[:cnt.value]}
 
 
 class Graph:

@@ -1,0 +1,89 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+include/geer.h declares, and rejects malformed graphs before touching a GPU."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2312_06123_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "geer.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(geer_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2312_06123_amd import geer as G
+
+    names = _declared()
+    assert len(names) >= 12
+    lib = ctypes.CDLL(G.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(names) <= set(G.EXPORTED)
+
+
+def test_version_and_error_strings():
+    from paper_2312_06123_amd import geer as G
+
+    assert "gfx950" in G.geer_version()
+    p = G.geer_params_default()
+    assert p.delta == 0.01 and p.tau == 5 and p.schedule == G.GEER_SCHEDULE_GREEDY
+
+
+def _csr(n, rows):
+    rp = np.zeros(n + 1, dtype=np.int32)
+    for v, r in enumerate(rows):
+        rp[v + 1] = rp[v] + len(r)
+    ci = np.array([u for r in rows for u in r], dtype=np.int32)
+    return rp, ci
+
+
+@pytest.mark.parametrize("rows,status", [
+    ([[1], []], "GEER_E_GRAPH"),                 # degree 0
+    ([[1], [0, 1]], "GEER_E_GRAPH"),             # self-loop
+    ([[1, 1], [0, 0]], "GEER_E_GRAPH"),          # duplicate entry
+    ([[2, 1], [0], [0]], "GEER_E_GRAPH"),        # unsorted row
+    ([[1, 2], [0], [1]], "GEER_E_GRAPH"),        # asymmetric
+    ([[1], [0], [3], [2]], "GEER_E_NOT_CONNECTED"),
+])
+def test_graph_validation_rejects(rows, status):
+    from paper_2312_06123_amd import geer as G
+
+    rp, ci = _csr(len(rows), rows)
+    with pytest.raises(G.GeerError) as e:
+        G.geer_graph_create(len(rows), rp, ci)
+    assert e.value.status == getattr(G, status)
+
+
+def test_graph_create_argument_errors():
+    from paper_2312_06123_amd import geer as G
+
+    with pytest.raises(G.GeerError) as e:
+        G.geer_graph_create(1, np.array([0, 0], np.int32), np.zeros(0, np.int32))
+    assert e.value.status == G.GEER_E_INVALID_ARG
+
+
+def test_generators_are_canonical_and_seeded():
+    for g in (I.erdos_renyi_path(500, 6, 1), I.chung_lu(2000, 2.1, 8, 2), I.rmat(10, 8, 0.57, 0.19, 0.19, 3)):
+        deg = g.degrees()
+        assert deg.min() >= 1
+        for v in range(0, g.n, max(1, g.n // 50)):
+            row = g.col_idx[g.row_ptr[v]:g.row_ptr[v + 1]]
+            assert np.all(np.diff(row) > 0) and v not in row
+            for u in row:
+                assert v in g.col_idx[g.row_ptr[u]:g.row_ptr[u + 1]]
+    a = I.chung_lu(3000, 2.1, 10, 9)
+    b = I.chung_lu(3000, 2.1, 10, 9)
+    assert np.array_equal(a.col_idx, b.col_idx)
+    e = I.erdos_renyi_path(1000, 10, 5)
+    assert e.m == 5000
+    s, t = I.uniform_pairs(100, 1000, 4)
+    assert np.all(s != t) and s.max() < 100
