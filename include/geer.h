@@ -161,7 +161,9 @@ geer_status geer_query(geer_graph *g, int64_t nq, const int32_t *s, const int32_
 /* As geer_query with device inputs and outputs, enqueued on params->stream
  * (or the library stream).  d_s, d_t: device int32[nq]; d_eps: device
  * double[nq]; d_r_out: device double[nq]; d_stats: device
- * geer_query_stats[nq] or NULL.  Node ids and eps are validated on the device;
+ * geer_query_stats[nq] or NULL.  With params->stream == NULL the work is
+ * ordered after everything already queued on the legacy default stream.
+ * Node ids and eps are validated on the device;
  * an invalid entry makes the call return GEER_E_INVALID_ARG after the stream
  * has drained (outputs then hold NaN for the invalid queries).  The call
  * returns when the work has finished. */

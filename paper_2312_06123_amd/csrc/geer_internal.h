@@ -76,6 +76,9 @@ struct Workspace {
     DevBuf zpart;     // AMC: per-chunk (sum Z, sum Z^2)
     DevBuf misc;      // small scalars (active masks, totals)
     DevBuf io;        // staging for host inputs/outputs
+    DevBuf acc;       // sparse hop: n x kCols fixed-point accumulators (kept all zero)
+    bool acc_zeroed = false;
+    std::vector<char> a_dirty;  // per slot: buffer A was written by a dense hop
     int slots = 0;
     int value_size = 0;
     int64_t nq_cap = 0;
@@ -94,6 +97,8 @@ enum ProfKind {
     PK_AMC_STOP,
     PK_FEATURES,
     PK_MLP,
+    PK_HOP2_SPARSE,
+    PK_HOP2_LDS,
     PK_COUNT
 };
 
@@ -142,6 +147,7 @@ struct geer_graph {
     int32_t *d_seg_end = nullptr;          // [n_seg] one past the last entry
     int32_t n_seg = 0;
     int64_t nnz_heavy = 0;                 // CSR entries in heavy rows
+    int fx_shift = 40;                     // fixed-point scale 2^F of the sparse hop
     geer::Workspace ws;
     geer::Profiler prof;
 };
@@ -256,6 +262,14 @@ geer_status launch_hop_dense(geer_graph *g, const HopArgs &a, int value_size, hi
 geer_status launch_epilogue(geer_graph *g, const QueryCtx &c, int64_t q0, int nb, int hop,
                             const void *vec, int64_t vec_elem_off, uint64_t *mask,
                             int value_size, int dense, hipStream_t st);
+geer_status launch_hop2_sparse(geer_graph *g, const QueryCtx &c, int64_t q0, const uint64_t *mask,
+                               void *out, uint32_t *out_bits, int value_size, int mode,
+                               hipStream_t st);
+geer_status launch_zero(geer_graph *g, void *p, size_t bytes, hipStream_t st);
+geer_status launch_hop2_lds(geer_graph *g, const QueryCtx &c, int64_t q0, const uint64_t *mask,
+                            void *out, uint32_t *out_bits, int value_size, hipStream_t st);
+geer_status launch_colstat(geer_graph *g, const uint64_t *mask, int prows, hipStream_t st);
+constexpr int kHashLoadMax = 9830;  // columns with more hop-2 work use the global path
 geer_status launch_column_top2(geer_graph *g, const void *vec, int ncols, int value_size,
                                hipStream_t st);
 

@@ -165,6 +165,10 @@ static geer_status build_graph(geer_graph *g, const int32_t *rp, const int32_t *
         invf[v] = (float)invd[v];
     }
     g->max_deg = maxd;
+    // sparse-hop fixed point: a sum of at most max_deg terms, each <= 1, must fit 62 bits
+    int bits = 0;
+    while ((1ll << bits) <= (long long)maxd) ++bits;
+    g->fx_shift = 62 - bits;
     GEER_TRY(upload(&g->d_inv_deg_f, invf.data(), invf.size()));
     GEER_TRY(upload(&g->d_inv_deg_d, invd.data(), invd.size()));
 
@@ -254,9 +258,9 @@ void geer_graph_destroy(geer_graph *g)
                     g->d_seg_end};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
-    DevBuf *bufs[] = {&g->ws.pool,  &g->ws.bits,      &g->ws.part,  &g->ws.segbuf,
+    DevBuf *bufs[] = {&g->ws.pool,    &g->ws.bits,   &g->ws.part,      &g->ws.segbuf,
                       &g->ws.colstat, &g->ws.qstate, &g->ws.chunk_off, &g->ws.zpart,
-                      &g->ws.misc,  &g->ws.io};
+                      &g->ws.misc,    &g->ws.io,     &g->ws.acc};
     for (DevBuf *b : bufs) b->release();
     for (ProfRec &r : g->prof.recs) {
         (void)hipEventDestroy(r.a);
@@ -288,7 +292,7 @@ geer_status geer_profile_read(geer_graph *g, geer_kernel_profile *out, int32_t c
     GEER_TRY(prof_flush(g));
     static const char *names[PK_COUNT] = {"hop_light", "hop_segments", "hop_heavy_fin", "hop1",
                                           "colstat", "epilogue", "walk", "amc_plan", "amc_stop",
-                                          "features", "mlp"};
+                                          "features", "mlp", "hop2_global", "hop2_lds"};
     int32_t k = 0;
     for (int i = 0; i < PK_COUNT && k < cap; ++i) {
         geer_kernel_profile &r = out[k++];

@@ -18,7 +18,7 @@ geer_status ensure_qstate(geer_graph *g, int64_t nq, QState *qs)
     const int64_t cap = std::max<int64_t>(nq, 1);
     const size_t per = 12 * sizeof(int32_t) + 4 * sizeof(int64_t) + 10 * sizeof(double);
     GEER_TRY(ws.qstate.reserve((size_t)cap * per + 64));
-    GEER_TRY(ws.misc.reserve(kMiscWords * sizeof(int64_t)));
+    GEER_TRY(ws.misc.reserve((kMiscWords + 1024) * sizeof(int64_t)));
     GEER_TRY(ws.colstat.reserve(kCols * (2 * sizeof(double) + sizeof(int64_t))));
     char *p = ws.qstate.as<char>();
     auto take = [&](auto *&dst, size_t elem) {
@@ -71,7 +71,9 @@ geer_status ensure_slots(geer_graph *g, int slots, int value_size)
         GEER_HIP(hipMemset(ws.bits.ptr, 0, ws.bits.bytes));
         ws.slots = slots;
         ws.value_size = value_size;
+        ws.a_dirty.assign(slots, 0);
     }
+    if ((int)ws.a_dirty.size() < slots) ws.a_dirty.resize(slots, 0);
     return GEER_OK;
 }
 
@@ -108,44 +110,126 @@ static int64_t host_mask(geer_graph *g, uint64_t *d_mask, hipStream_t st, geer_s
     return (int64_t)m;
 }
 
-// SMM of one batch (pairs q0 .. q0+nb-1) in slot `slot`: hop 1 scatter, then
-// dense hops until every pair of the batch has stopped.  Returns the number
-// of hops performed.
+// What a batch left in its slot (needed to restore the all-zero state of the
+// sparse buffers after the group's AMC phase).
+struct BatchRec {
+    int64_t q0 = 0;
+    int nb = 0;
+    bool hop1 = false;          // H1 holds scattered entries
+    uint64_t hop2_sparse = 0;   // pairs whose hop-2 vectors were pushed into A
+};
+
+// SMM of one batch (pairs q0 .. q0+nb-1) in slot `slot`: hop 1 scatter, hop 2
+// as a sparse push when its work is small, then dense hops until every pair
+// of the batch has stopped.
 static geer_status smm_batch(geer_graph *g, const QueryCtx &c, const SlotView &sv, int slot,
                              int64_t q0, int nb, int col_tile, int max_hops, hipStream_t st,
-                             int *hops_done)
+                             int *hops_done, BatchRec *rec)
 {
-    uint64_t *d_mask = reinterpret_cast<uint64_t *>(g->ws.misc.as<int64_t>());
+    Workspace &ws = g->ws;
+    uint64_t *d_mask = reinterpret_cast<uint64_t *>(ws.misc.as<int64_t>());
+    uint64_t *d_slot_mask = reinterpret_cast<uint64_t *>(ws.misc.as<int64_t>()) + kMiscWords + slot;
+    static thread_local uint64_t host_paths[4];
+    rec->q0 = q0;
+    rec->nb = nb;
+    rec->hop1 = false;
+    rec->hop2_sparse = 0;
     hipLaunchKernelGGL(k_batch_mask, dim3(1), dim3(64), 0, st, c.qs, q0, nb, d_mask);
     GEER_HIP(hipGetLastError());
     *hops_done = 0;
     geer_status err = GEER_OK;
     if (host_mask(g, d_mask, st, &err) == 0) return err;
     GEER_TRY(launch_hop1(g, c, q0, nb, sv.buf(slot, 0), sv.bw(slot, 0), d_mask, sv.vs, false, st));
+    rec->hop1 = true;
     GEER_TRY(launch_epilogue(g, c, q0, nb, 1, sv.buf(slot, 0), sv.elem_off(slot, 0), d_mask, sv.vs,
                              0, st));
     *hops_done = 1;
     for (int hop = 2;; ++hop) {
-        int64_t m = host_mask(g, d_mask, st, &err);
-        if (err != GEER_OK) return err;
+        int64_t sd[kCols];
+        uint64_t m = 0;
+        if (hop == 2) {
+            // mask and the hop-1 support degree sums (= the push work of hop 2)
+            GEER_HIP(hipMemcpyAsync(sd, (char *)ws.colstat.ptr + 2 * kCols * sizeof(double),
+                                    sizeof(sd), hipMemcpyDeviceToHost, st));
+            GEER_HIP(hipMemcpyAsync(&m, d_mask, sizeof(m), hipMemcpyDeviceToHost, st));
+            GEER_HIP(hipStreamSynchronize(st));
+        } else {
+            m = (uint64_t)host_mask(g, d_mask, st, &err);
+            if (err != GEER_OK) return err;
+        }
         if (m == 0) break;
         if (hop > max_hops)
             return fail(GEER_E_DEVICE, "SMM batch still active after the largest possible l");
-        const int win = hop == 2 ? 0 : (hop % 2 == 0 ? 2 : 1);  // input buffer
-        const int wout = hop % 2 == 0 ? 1 : 2;                  // output buffer
-        HopArgs a;
-        a.in = sv.buf(slot, win);
-        a.out = sv.buf(slot, wout);
-        a.in_bits = sv.bw(slot, win);
-        a.out_bits = sv.bw(slot, wout);
-        a.mask = d_mask;
-        a.host_mask = (uint64_t)m;
-        a.col0 = 0;
-        a.col_tile = col_tile;
-        GEER_TRY(launch_hop_dense(g, a, sv.vs, st));
-        GEER_TRY(launch_epilogue(g, c, q0, nb, hop, a.out, sv.elem_off(slot, wout), d_mask, sv.vs,
-                                 1, st));
+        const int wout = hop % 2 == 0 ? 1 : 2;  // output buffer: A on even hops, B on odd
+        bool sparse = false;
+        uint64_t m_lds[2] = {0, 0}, m_glob[2] = {0, 0};  // per-column path masks
+        if (hop == 2 && sv.vs == 4) {
+            double work = 0.0;
+            for (int c2 = 0; c2 < kCols; ++c2) {
+                if (!((m >> (c2 >> 1)) & 1ull)) continue;
+                work += (double)sd[c2];
+                if (sd[c2] <= kHashLoadMax) m_lds[c2 >> 6] |= 1ull << (c2 & 63);
+                else m_glob[c2 >> 6] |= 1ull << (c2 & 63);
+            }
+            sparse = work <= 2.0 * (double)g->nnz;
+        }
+        if (sparse) {
+            if (ws.a_dirty[slot]) {
+                GEER_TRY(launch_zero(g, sv.buf(slot, 1), (size_t)g->n * kCols * sv.vs, st));
+                GEER_TRY(launch_zero(g, sv.bw(slot, 1), (size_t)g->n * kBitWords * 4, st));
+                ws.a_dirty[slot] = 0;
+            }
+            // per-pair path masks live next to the batch mask
+            uint64_t *d_paths = d_mask + 1;  // words 1-2: LDS columns, 3-4: global columns
+            host_paths[0] = m_lds[0];
+            host_paths[1] = m_lds[1];
+            host_paths[2] = m_glob[0];
+            host_paths[3] = m_glob[1];
+            GEER_HIP(hipMemcpyAsync(d_paths, host_paths, 4 * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+            GEER_HIP(hipMemcpyAsync(d_slot_mask, d_mask, sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+            const size_t part_bytes = (size_t)8 * kCols * (2 * sizeof(double) + sizeof(int64_t));
+            GEER_TRY(ws.part.reserve(std::max(ws.part.bytes, part_bytes)));
+            GEER_TRY(launch_zero(g, ws.part.ptr, part_bytes, st));
+            if (m_lds[0] | m_lds[1])
+                GEER_TRY(launch_hop2_lds(g, c, q0, d_paths, sv.buf(slot, 1), sv.bw(slot, 1), sv.vs, st));
+            if (m_glob[0] | m_glob[1]) {
+                GEER_TRY(launch_hop2_sparse(g, c, q0, d_paths + 2, sv.buf(slot, 1), sv.bw(slot, 1), sv.vs, 0, st));
+                GEER_TRY(launch_hop2_sparse(g, c, q0, d_paths + 2, sv.buf(slot, 1), sv.bw(slot, 1), sv.vs, 1, st));
+            }
+            GEER_TRY(launch_colstat(g, d_mask, 8, st));
+            rec->hop2_sparse = m;
+        } else {
+            const int win = hop == 2 ? 0 : (hop % 2 == 0 ? 2 : 1);  // input buffer
+            HopArgs a;
+            a.in = sv.buf(slot, win);
+            a.out = sv.buf(slot, wout);
+            a.in_bits = sv.bw(slot, win);
+            a.out_bits = sv.bw(slot, wout);
+            a.mask = d_mask;
+            a.host_mask = m;
+            a.col0 = 0;
+            a.col_tile = col_tile;
+            GEER_TRY(launch_hop_dense(g, a, sv.vs, st));
+            if (wout == 1) ws.a_dirty[slot] = 1;
+        }
+        GEER_TRY(launch_epilogue(g, c, q0, nb, hop, sv.buf(slot, wout), sv.elem_off(slot, wout), d_mask,
+                                 sv.vs, 1, st));
         *hops_done = hop;
+    }
+    return GEER_OK;
+}
+
+// Restore H1 and the sparse part of A of a finished batch to zero.
+static geer_status cleanup_batch(geer_graph *g, const QueryCtx &c, const SlotView &sv, int slot,
+                                 const BatchRec &rec, hipStream_t st)
+{
+    if (rec.hop1)
+        GEER_TRY(launch_hop1(g, c, rec.q0, rec.nb, sv.buf(slot, 0), sv.bw(slot, 0), nullptr, sv.vs,
+                             true, st));
+    if (rec.hop2_sparse && !g->ws.a_dirty[slot]) {
+        uint64_t *d_slot_mask = reinterpret_cast<uint64_t *>(g->ws.misc.as<int64_t>()) + kMiscWords + slot;
+        GEER_TRY(launch_hop2_sparse(g, c, rec.q0, d_slot_mask, sv.buf(slot, 1), sv.bw(slot, 1), sv.vs,
+                                    2, st));
     }
     return GEER_OK;
 }
@@ -192,18 +276,20 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
     const int vs = (p.flags & GEER_FLAG_FP64_VECTORS) ? 8 : 4;
     const int B = p.batch_queries ? p.batch_queries : kMaxPairs;
     const int64_t nbatches = (c.nq + B - 1) / B;
-    const int G = p.group_batches ? p.group_batches : default_group_batches(g, vs, nbatches);
+    const int G = std::min(1024, p.group_batches ? p.group_batches : default_group_batches(g, vs, nbatches));
     const int col_tile = p.col_tile ? p.col_tile : default_col_tile(g, vs);
     GEER_TRY(ensure_slots(g, G, vs));
     GEER_TRY(launch_init_queries(g, c, d_fixed, -1, st));
     SlotView sv{g->ws.pool.as<char>(), g->ws.bits.as<uint32_t>(), (size_t)g->n, vs};
     for (int64_t b0 = 0; b0 < nbatches; b0 += G) {
         const int64_t b1 = std::min<int64_t>(nbatches, b0 + G);
+        std::vector<BatchRec> recs((size_t)(b1 - b0));
         for (int64_t b = b0; b < b1; ++b) {
             const int64_t q0 = b * B;
             const int nb = (int)std::min<int64_t>(B, c.nq - q0);
             int hops = 0;
-            GEER_TRY(smm_batch(g, c, sv, (int)(b - b0), q0, nb, col_tile, max_hops, st, &hops));
+            GEER_TRY(smm_batch(g, c, sv, (int)(b - b0), q0, nb, col_tile, max_hops, st, &hops,
+                               &recs[(size_t)(b - b0)]));
         }
         AmcGroup grp;
         grp.q0 = b0 * B;
@@ -211,13 +297,9 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
         grp.pool = sv.pool;
         grp.value_size = vs;
         GEER_TRY(amc_phase(g, c, grp, st, p.walk_ilp));
-        // restore the group's H1 buffers to all-zero
-        for (int64_t b = b0; b < b1; ++b) {
-            const int64_t q0 = b * B;
-            const int nb = (int)std::min<int64_t>(B, c.nq - q0);
-            GEER_TRY(launch_hop1(g, c, q0, nb, sv.buf((int)(b - b0), 0), sv.bw((int)(b - b0), 0),
-                                 nullptr, vs, true, st));
-        }
+        // restore the group's sparse buffers to all-zero
+        for (int64_t b = b0; b < b1; ++b)
+            GEER_TRY(cleanup_batch(g, c, sv, (int)(b - b0), recs[(size_t)(b - b0)], st));
     }
     return GEER_OK;
 }
@@ -328,6 +410,15 @@ geer_status geer_query_device(geer_graph *g, int64_t nq, const int32_t *d_s, con
     c.schedule = p.schedule;
     c.seed = p.seed;
     c.qid_offset = p.qid_offset;
+    if (!p.stream) {
+        // no stream given: order after all work already queued on the legacy
+        // default stream (where the caller's inputs were most likely produced)
+        hipEvent_t ev;
+        GEER_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        GEER_HIP(hipEventRecord(ev, nullptr));
+        GEER_HIP(hipStreamWaitEvent(st, ev, 0));
+        GEER_HIP(hipEventDestroy(ev));
+    }
     GEER_TRY(g->ws.io.reserve((size_t)nq * sizeof(int32_t) + 256));
     int32_t *d_fixed = g->ws.io.as<int32_t>();
     GEER_HIP(hipMemcpyAsync(c.qs.s, d_s, nq * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
@@ -387,7 +478,8 @@ geer_status geer_smm(geer_graph *g, int32_t nq, const int32_t *s, const int32_t 
     SlotView sv{g->ws.pool.as<char>(), g->ws.bits.as<uint32_t>(), (size_t)g->n, vs};
     const int tile = col_tile ? col_tile : default_col_tile(g, vs);
     int done = 0;
-    if (hops > 0) GEER_TRY(smm_batch(g, c, sv, 0, 0, nq, tile, hops, st, &done));
+    BatchRec rec;
+    if (hops > 0) GEER_TRY(smm_batch(g, c, sv, 0, 0, nq, tile, hops, st, &done, &rec));
     GEER_HIP(hipStreamSynchronize(st));
     const size_t n = (size_t)g->n;
     if (hops == 0) {
@@ -443,9 +535,9 @@ geer_status geer_smm(geer_graph *g, int32_t nq, const int32_t *s, const int32_t 
             }
         }
     }
-    // restore H1 to zero
+    // restore the sparse buffers to zero
     if (hops > 0) {
-        GEER_TRY(launch_hop1(g, c, 0, nq, sv.buf(0, 0), sv.bw(0, 0), nullptr, vs, true, st));
+        GEER_TRY(cleanup_batch(g, c, sv, 0, rec, st));
         GEER_HIP(hipStreamSynchronize(st));
     }
     return GEER_OK;
@@ -563,6 +655,7 @@ extern "C" geer_status geer_amc(geer_graph *g, int32_t s, int32_t t, const doubl
     }
     GEER_HIP(hipMemcpy2D(sv.buf(0, 1), (size_t)kCols * vs, host.data(), (size_t)2 * vs, (size_t)2 * vs,
                          (size_t)n, hipMemcpyHostToDevice));
+    g->ws.a_dirty[0] = 1;  // A now holds dense caller vectors
     GEER_HIP(hipMemcpyAsync(c.qs.s, &s, sizeof(int32_t), hipMemcpyHostToDevice, st));
     GEER_HIP(hipMemcpyAsync(c.qs.t, &t, sizeof(int32_t), hipMemcpyHostToDevice, st));
     GEER_TRY(launch_column_top2(g, sv.buf(0, 1), 2, vs, st));

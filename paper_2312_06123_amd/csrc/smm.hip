@@ -23,14 +23,13 @@ template <class T> struct Vec2;
 template <> struct Vec2<float> { using type = float2; };
 template <> struct Vec2<double> { using type = double2; };
 
+// Largest / second-largest with repeats counted (the second largest of
+// {3, 3} is 3), branch-free: the smaller of (m1, v) competes for second place.
 template <class T> __device__ __forceinline__ void top2_push(T &m1, T &m2, T v)
 {
-    if (v > m1) {
-        m2 = m1;
-        m1 = v;
-    } else if (v > m2) {
-        m2 = v;
-    }
+    const T lo = v < m1 ? v : m1;
+    m1 = v > m1 ? v : m1;
+    m2 = lo > m2 ? lo : m2;
 }
 
 // ----------------------------------------------------------------------------
@@ -320,6 +319,10 @@ __device__ __forceinline__ void write_block_stats(int lane, int wave, int slot, 
     }
 }
 
+// Light rows: a group of KT/2 lanes owns one row (one column pair per lane),
+// so a wavefront has 64/(KT/2) rows in flight.  Trip counts are uniform over
+// the wavefront (the largest degree of its rows), so the index broadcasts
+// always run with every lane active.
 template <class T, int KT>
 __global__ __launch_bounds__(256) void k_hop_light(
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
@@ -330,27 +333,95 @@ __global__ __launch_bounds__(256) void k_hop_light(
 {
     using T2 = typename Vec2<T>::type;
     constexpr int LPR = KT / 2;
+    constexpr int RPW = 64 / LPR;
+    constexpr int U = 8;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int slot = lane / LPR;
-    const int col = col0 + 2 * (lane % LPR);
-    const int bw = col >> 5;
+    const int grp = lane / LPR, li = lane % LPR;
+    const int col = col0 + 2 * li;
+    const int bw = col >> 5, bsh = col & 31;
     const bool act = ((*mask_p) >> (col >> 1)) & 1ull;
     T m1s = 0, m2s = 0, m1t = 0, m2t = 0;
     uint32_t sds = 0, sdt = 0;
-    for (int32_t r = blockIdx.x * 4 + wave; r < nrows; r += gridDim.x * 4) {
-        const int32_t v = rows[r];
-        const int32_t b = row_ptr[v], e = row_ptr[v + 1];
+    const int64_t stride = (int64_t)gridDim.x * 4 * RPW;
+    for (int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * RPW; r0 < nrows; r0 += stride) {
+        const int64_t r = r0 + grp;
+        const bool has = r < nrows;
+        const int32_t v = has ? rows[r] : 0;
+        const int32_t b = has ? row_ptr[v] : 0;
+        const int32_t d = has ? row_ptr[v + 1] - b : 0;
+        int32_t dmax = d;
+#pragma unroll
+        for (int o = LPR; o < 64; o <<= 1) dmax = max(dmax, __shfl_xor(dmax, o));
         T2 acc;
         acc.x = T(0);
         acc.y = T(0);
         uint32_t bacc = 0;
-        gather_range<T, KT>(col_idx, in, in_bits, b, e, lane, slot, col, bw, acc, bacc);
-        reduce_slots<T, KT>(acc, bacc);
-        emit_row<T, KT>(out, out_bits, v, e - b, inv_deg[v], acc, bacc, lane, slot, col, bw, act,
-                        m1s, m2s, m1t, m2t, sds, sdt);
+        for (int32_t k0 = 0; k0 < dmax; k0 += LPR) {
+            const int32_t myidx = (k0 + li < d) ? col_idx[b + k0 + li] : 0;
+            for (int kk = 0; kk < LPR && k0 + kk < dmax; kk += U) {
+                int32_t u[U];
+                bool ok[U];
+#pragma unroll
+                for (int i = 0; i < U; ++i) {
+                    ok[i] = k0 + kk + i < d;
+                    u[i] = __shfl(myidx, grp * LPR + kk + i);
+                }
+                T2 x[U];
+                uint32_t w[U];
+#pragma unroll
+                for (int i = 0; i < U; ++i) {
+                    if (ok[i]) {
+                        x[i] = *reinterpret_cast<const T2 *>(in + (size_t)u[i] * kCols + col);
+                        w[i] = in_bits[(size_t)u[i] * kBitWords + bw];
+                    } else {
+                        x[i].x = T(0);
+                        x[i].y = T(0);
+                        w[i] = 0u;
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < U; ++i) {
+                    acc.x += x[i].x;
+                    acc.y += x[i].y;
+                    bacc |= w[i];
+                }
+            }
+        }
+        // emit the row of this group
+        const uint32_t mine = (act && has) ? ((bacc >> bsh) & 3u) : 0u;
+        uint32_t word = mine << bsh;
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) word |= __shfl_xor(word, o);
+        if (has) {
+            const T idg = inv_deg[v];
+            if (act) {
+                T2 y;
+                y.x = acc.x * idg;
+                y.y = acc.y * idg;
+                *reinterpret_cast<T2 *>(out + (size_t)v * kCols + col) = y;
+                top2_push(m1s, m2s, y.x);
+                top2_push(m1t, m2t, y.y);
+                if (mine & 1u) sds += (uint32_t)d;
+                if (mine & 2u) sdt += (uint32_t)d;
+            }
+            if ((li & 15) == 0) out_bits[(size_t)v * kBitWords + bw] = word;
+        }
     }
-    write_block_stats<T, KT>(lane, wave, slot, col, m1s, m2s, m1t, m2t, sds, sdt, blockIdx.x,
-                             p_m1, p_m2, p_sd);
+    // merge the statistics of the row groups (disjoint row sets) into group 0
+#pragma unroll
+    for (int o = LPR; o < 64; o <<= 1) {
+        T a1 = __shfl_xor(m1s, o), a2 = __shfl_xor(m2s, o);
+        T b1 = __shfl_xor(m1t, o), b2 = __shfl_xor(m2t, o);
+        uint32_t c1 = __shfl_xor(sds, o), c2 = __shfl_xor(sdt, o);
+        top2_push(m1s, m2s, a1);
+        top2_push(m1s, m2s, a2);
+        top2_push(m1t, m2t, b1);
+        top2_push(m1t, m2t, b2);
+        sds += c1;
+        sdt += c2;
+    }
+    write_block_stats<T, KT>(lane, wave, grp, col, m1s, m2s, m1t, m2t, sds, sdt, blockIdx.x, p_m1,
+                             p_m2, p_sd);
 }
 
 // Heavy rows, pass 1: partial sums of 256-entry segments.
@@ -549,6 +620,10 @@ geer_status launch_hop_dense(geer_graph *g, const HopArgs &a, int value_size, hi
                                (kCols * (size_t)value_size + kBitWords * sizeof(uint32_t))));
     const int kt = a.col_tile;
     for (int c0 = 0; c0 < kCols; c0 += kt) {
+        // a tile without an active pair has nothing to compute (its columns
+        // are not read again: stopped pairs keep their vectors elsewhere)
+        const uint64_t tile_pairs = kt == 128 ? ~0ull : (((1ull << (kt / 2)) - 1ull) << (c0 / 2));
+        if ((a.host_mask & tile_pairs) == 0) continue;
         HopArgs t = a;
         t.col0 = c0;
         geer_status s = GEER_E_INVALID_ARG;
@@ -719,6 +794,379 @@ geer_status launch_column_top2(geer_graph *g, const void *vec, int ncols, int va
     else
         hipLaunchKernelGGL(k_column_top2<double>, dim3(ncols), dim3(256), 0, st,
                            (const double *)vec, g->n, cs_m1, cs_m2);
+    GEER_HIP(hipGetLastError());
+    return GEER_OK;
+}
+
+}  // namespace geer
+
+namespace geer {
+
+// ----------------------------------------------------------------------------
+// Sparse hop 2 (push from the hop-1 frontier).  After one product the vector
+// of column c is x1(v) = 1/d(v) on N(u) (u = s or t), so
+//     x2(w) = (1/d(w)) * sum_{v in N(u), w in N(v)} 1/d(v).
+// The work is sum_{v in N(u)} d(v) instead of a pass over the whole graph.
+// Contributions are added as unsigned fixed point (1/d(v) * 2^F rounded once
+// per v) with integer atomics, so every sum is exact and independent of the
+// order of the additions; the first visitor of an entry takes the sum with an
+// exchange (which also resets the accumulator to zero), scales it by 1/d(w)
+// in FP64, rounds once to the vector type and records the statistics.
+// ----------------------------------------------------------------------------
+
+constexpr int kPushSplit = 8;  // blocks per column
+
+__device__ __forceinline__ unsigned long long fixed_inv_deg(double inv_d, int shift)
+{
+    return __double2ull_rn(ldexp(inv_d, shift));
+}
+
+constexpr int kPushChunk = 2048;  // neighbours of u staged in LDS per round
+
+// mode 0: accumulate; mode 1: convert + stats; mode 2: clear the output entries.
+// The work of column c is the concatenation of the rows N(v), v in N(u).  A
+// block stages a chunk of N(u) and the prefix sums of the degrees in LDS and
+// spreads the flattened entries over all of its lanes (and the kPushSplit
+// blocks of the column), so hub rows do not serialise on one wavefront.
+template <class T, int MODE>
+__global__ __launch_bounds__(256) void k_hop2_sparse(
+    QState qs, int64_t q0, const uint64_t *__restrict__ mask_p,
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
+    const double *__restrict__ inv_deg_d, unsigned long long *__restrict__ acc, int shift,
+    T *__restrict__ out, uint32_t *__restrict__ out_bits, double *__restrict__ p_m1,
+    double *__restrict__ p_m2, int64_t *__restrict__ p_sd)
+{
+    __shared__ int32_t s_v[kPushChunk];
+    __shared__ int32_t s_beg[kPushChunk];
+    __shared__ int32_t s_pre[kPushChunk + 1];
+    __shared__ int32_t s_tmp[256];
+    const int c = blockIdx.x;
+    const int k = blockIdx.y;
+    const int j = c >> 1;
+    // modes 0/1: per-column path mask (two words); mode 2: the batch's pair mask
+    const bool act = MODE == 2 ? (((*mask_p) >> j) & 1ull) : ((mask_p[c >> 6] >> (c & 63)) & 1ull);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    T m1 = 0, m2 = 0;
+    int64_t sd = 0;
+    if (act) {
+        const int64_t q = q0 + j;
+        const int32_t u = (c & 1) ? qs.t[q] : qs.s[q];
+        const int32_t b0 = row_ptr[u], du = row_ptr[u + 1] - b0;
+        const uint32_t bit = 1u << (c & 31);
+        for (int32_t base = 0; base < du; base += kPushChunk) {
+            const int cnt = min(kPushChunk, du - base);
+            // stage v, its row start and degree; 256-thread scan of the degrees
+            const int per = (cnt + 255) / 256;
+            int32_t local = 0;
+            for (int i = tid * per; i < min(cnt, (tid + 1) * per); ++i) {
+                const int32_t v = col_idx[b0 + base + i];
+                const int32_t rb = row_ptr[v];
+                s_v[i] = v;
+                s_beg[i] = rb;
+                s_pre[i] = row_ptr[v + 1] - rb;  // degree for now
+                local += s_pre[i];
+            }
+            s_tmp[tid] = local;
+            __syncthreads();
+            for (int o = 1; o < 256; o <<= 1) {
+                int32_t add = tid >= o ? s_tmp[tid - o] : 0;
+                __syncthreads();
+                s_tmp[tid] += add;
+                __syncthreads();
+            }
+            int32_t run = s_tmp[tid] - local;
+            for (int i = tid * per; i < min(cnt, (tid + 1) * per); ++i) {
+                const int32_t d = s_pre[i];
+                s_pre[i] = run;
+                run += d;
+            }
+            if (tid == 255) s_pre[cnt] = s_tmp[255];
+            __syncthreads();
+            const int32_t total = s_pre[cnt];
+            for (int32_t p = k * 256 + tid; p < total; p += kPushSplit * 256) {
+                // entry p lies in row s_v[i] with s_pre[i] <= p < s_pre[i+1]
+                int lo = 0, hi = cnt;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_pre[mid] <= p) lo = mid;
+                    else hi = mid;
+                }
+                const int32_t v = s_v[lo];
+                const int32_t w = col_idx[s_beg[lo] + (p - s_pre[lo])];
+                const size_t off = (size_t)w * kCols + c;
+                if (MODE == 0) {
+                    atomicAdd(acc + off, fixed_inv_deg(inv_deg_d[v], shift));
+                } else if (MODE == 1) {
+                    const unsigned long long tot = atomicExch(acc + off, 0ull);
+                    if (tot != 0ull) {
+                        const T val = (T)(ldexp((double)tot, -shift) * inv_deg_d[w]);
+                        out[off] = val;
+                        atomicOr(out_bits + (size_t)w * kBitWords + (c >> 5), bit);
+                        top2_push(m1, m2, val);
+                        sd += row_ptr[w + 1] - row_ptr[w];
+                    }
+                } else {
+                    out[off] = T(0);
+                    atomicAnd(out_bits + (size_t)w * kBitWords + (c >> 5), ~bit);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (MODE != 1 || !act) return;
+    // block reduction of the statistics -> partial row k of column c
+    for (int o = 32; o > 0; o >>= 1) {
+        T o1 = __shfl_xor(m1, o), o2 = __shfl_xor(m2, o);
+        int64_t osd = __shfl_xor(sd, o);
+        top2_push(m1, m2, o1);
+        top2_push(m1, m2, o2);
+        sd += osd;
+    }
+    __shared__ double s1[4], s2[4];
+    __shared__ int64_t ss[4];
+    if (lane == 0) {
+        s1[wave] = (double)m1;
+        s2[wave] = (double)m2;
+        ss[wave] = sd;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double a1 = s1[0], a2 = s2[0];
+        int64_t t = ss[0];
+        for (int w = 1; w < 4; ++w) {
+            top2_push(a1, a2, s1[w]);
+            top2_push(a1, a2, s2[w]);
+            t += ss[w];
+        }
+        const size_t o = (size_t)k * kCols + c;
+        p_m1[o] = a1;
+        p_m2[o] = a2;
+        p_sd[o] = t;
+    }
+}
+
+// Fused hop 2 for one column in LDS: the (w, 1/d(v)) contributions of the
+// column are accumulated in a hash table in LDS (key w, unsigned fixed-point
+// sum, 64-bit LDS atomics -- exact and order independent), then every table
+// entry is converted once.  Used when the column's work sum_{v in N(u)} d(v)
+// fits the table at half load; other columns take the global path.
+constexpr int kHashCap = 12288;  // 144 KB of the 160 KB LDS
+
+template <class T>
+__global__ __launch_bounds__(512) void k_hop2_lds(
+    QState qs, int64_t q0, const uint64_t *__restrict__ mask_p,
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
+    const double *__restrict__ inv_deg_d, int shift, T *__restrict__ out,
+    uint32_t *__restrict__ out_bits, double *__restrict__ p_m1, double *__restrict__ p_m2,
+    int64_t *__restrict__ p_sd)
+{
+    __shared__ int32_t s_key[kHashCap];
+    __shared__ unsigned long long s_val[kHashCap];
+    __shared__ int32_t s_pre[513];
+    __shared__ int32_t s_v[512];
+    __shared__ int32_t s_beg[512];
+    __shared__ int32_t s_tmp[512];
+    __shared__ double s1[8], s2[8];
+    __shared__ int64_t ss[8];
+    const int c = blockIdx.x;
+    const int j = c >> 1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool act = (mask_p[c >> 6] >> (c & 63)) & 1ull;  // per-column path mask
+    T m1 = 0, m2 = 0;
+    int64_t sd = 0;
+    if (act) {
+        for (int i = tid; i < kHashCap; i += 512) {
+            s_key[i] = -1;
+            s_val[i] = 0ull;
+        }
+        const int64_t q = q0 + j;
+        const int32_t u = (c & 1) ? qs.t[q] : qs.s[q];
+        const int32_t b0 = row_ptr[u], du = row_ptr[u + 1] - b0;
+        __syncthreads();
+        for (int32_t base = 0; base < du; base += 512) {
+            const int cnt = min(512, du - base);
+            int32_t local = 0;
+            for (int i = tid; i < min(cnt, tid + 1); ++i) {
+                const int32_t v = col_idx[b0 + base + i];
+                const int32_t rb = row_ptr[v];
+                s_v[i] = v;
+                s_beg[i] = rb;
+                s_pre[i] = row_ptr[v + 1] - rb;
+                local += s_pre[i];
+            }
+            s_tmp[tid] = local;
+            __syncthreads();
+            for (int o = 1; o < 512; o <<= 1) {
+                int32_t add = tid >= o ? s_tmp[tid - o] : 0;
+                __syncthreads();
+                s_tmp[tid] += add;
+                __syncthreads();
+            }
+            int32_t run = s_tmp[tid] - local;
+            for (int i = tid; i < min(cnt, tid + 1); ++i) {
+                const int32_t d = s_pre[i];
+                s_pre[i] = run;
+                run += d;
+            }
+            if (tid == 511) s_pre[cnt] = s_tmp[511];
+            __syncthreads();
+            const int32_t total = s_pre[cnt];
+            for (int32_t p = tid; p < total; p += 512) {
+                int lo = 0, hi = cnt;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_pre[mid] <= p) lo = mid;
+                    else hi = mid;
+                }
+                const int32_t v = s_v[lo];
+                const int32_t w = col_idx[s_beg[lo] + (p - s_pre[lo])];
+                // open addressing with linear probing; the table is never more
+                // than half full (checked by the caller), so a slot is found
+                uint32_t h = ((uint32_t)w * 2654435761u) % (uint32_t)kHashCap;
+                for (;;) {
+                    const int32_t k = s_key[h];
+                    if (k == w) break;
+                    if (k == -1) {
+                        const int32_t old = atomicCAS(&s_key[h], -1, w);
+                        if (old == -1 || old == w) break;
+                    }
+                    h = h + 1 == (uint32_t)kHashCap ? 0u : h + 1;
+                }
+                atomicAdd(&s_val[h], fixed_inv_deg(inv_deg_d[v], shift));
+            }
+            __syncthreads();
+        }
+        const uint32_t bit = 1u << (c & 31);
+        for (int i = tid; i < kHashCap; i += 512) {
+            const int32_t w = s_key[i];
+            if (w < 0) continue;
+            const T val = (T)(ldexp((double)s_val[i], -shift) * inv_deg_d[w]);
+            out[(size_t)w * kCols + c] = val;
+            atomicOr(out_bits + (size_t)w * kBitWords + (c >> 5), bit);
+            top2_push(m1, m2, val);
+            sd += row_ptr[w + 1] - row_ptr[w];
+        }
+    }
+    if (!act) return;
+    for (int o = 32; o > 0; o >>= 1) {
+        T o1 = __shfl_xor(m1, o), o2 = __shfl_xor(m2, o);
+        int64_t osd = __shfl_xor(sd, o);
+        top2_push(m1, m2, o1);
+        top2_push(m1, m2, o2);
+        sd += osd;
+    }
+    if (lane == 0) {
+        s1[wave] = (double)m1;
+        s2[wave] = (double)m2;
+        ss[wave] = sd;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double a1 = s1[0], a2 = s2[0];
+        int64_t t = ss[0];
+        for (int w = 1; w < 8; ++w) {
+            top2_push(a1, a2, s1[w]);
+            top2_push(a1, a2, s2[w]);
+            t += ss[w];
+        }
+        p_m1[c] = a1;  // partial row 0; the global path fills rows 1.. with zeros here
+        p_m2[c] = a2;
+        p_sd[c] = t;
+    }
+}
+
+geer_status launch_hop2_lds(geer_graph *g, const QueryCtx &c, int64_t q0, const uint64_t *mask,
+                            void *out, uint32_t *out_bits, int value_size, hipStream_t st)
+{
+    Workspace &ws = g->ws;
+    double *p_m1 = ws.part.as<double>();
+    const size_t prows = kPushSplit;
+    double *p_m2 = p_m1 + prows * kCols;
+    int64_t *p_sd = reinterpret_cast<int64_t *>(p_m2 + prows * kCols);
+    int tok = prof_begin(g, st);
+    if (value_size == 4)
+        hipLaunchKernelGGL(k_hop2_lds<float>, dim3(kCols), dim3(512), 0, st, c.qs, q0, mask,
+                           g->d_row_ptr, g->d_col_idx, g->d_inv_deg_d, g->fx_shift, (float *)out,
+                           out_bits, p_m1, p_m2, p_sd);
+    else
+        hipLaunchKernelGGL(k_hop2_lds<double>, dim3(kCols), dim3(512), 0, st, c.qs, q0, mask,
+                           g->d_row_ptr, g->d_col_idx, g->d_inv_deg_d, g->fx_shift, (double *)out,
+                           out_bits, p_m1, p_m2, p_sd);
+    prof_end(g, tok, PK_HOP2_LDS, 0.0, 0.0, st);
+    GEER_HIP(hipGetLastError());
+    return GEER_OK;
+}
+
+geer_status launch_hop2_sparse(geer_graph *g, const QueryCtx &c, int64_t q0, const uint64_t *mask,
+                               void *out, uint32_t *out_bits, int value_size, int mode,
+                               hipStream_t st)
+{
+    Workspace &ws = g->ws;
+    GEER_TRY(ws.acc.reserve((size_t)g->n * kCols * sizeof(unsigned long long)));
+    if (!ws.acc_zeroed) {
+        GEER_HIP(hipMemsetAsync(ws.acc.ptr, 0, ws.acc.bytes, st));
+        ws.acc_zeroed = true;
+    }
+    const size_t prows = kPushSplit;
+    GEER_TRY(ws.part.reserve(std::max(ws.part.bytes, prows * kCols * (2 * sizeof(double) + sizeof(int64_t)))));
+    double *p_m1 = ws.part.as<double>();
+    double *p_m2 = p_m1 + prows * kCols;
+    int64_t *p_sd = reinterpret_cast<int64_t *>(p_m2 + prows * kCols);
+    unsigned long long *acc = ws.acc.as<unsigned long long>();
+    const dim3 grid(kCols, kPushSplit);
+    int tok = prof_begin(g, st);
+#define GEER_PUSH(T_, M_)                                                                      \
+    hipLaunchKernelGGL((k_hop2_sparse<T_, M_>), grid, dim3(256), 0, st, c.qs, q0, mask,         \
+                       g->d_row_ptr, g->d_col_idx, g->d_inv_deg_d, acc, g->fx_shift, (T_ *)out, \
+                       out_bits, p_m1, p_m2, p_sd)
+    if (value_size == 4) {
+        if (mode == 0) GEER_PUSH(float, 0);
+        else if (mode == 1) GEER_PUSH(float, 1);
+        else GEER_PUSH(float, 2);
+    } else {
+        if (mode == 0) GEER_PUSH(double, 0);
+        else if (mode == 1) GEER_PUSH(double, 1);
+        else GEER_PUSH(double, 2);
+    }
+#undef GEER_PUSH
+    prof_end(g, tok, PK_HOP2_SPARSE, 0.0, 0.0, st);
+    GEER_HIP(hipGetLastError());
+    return GEER_OK;
+}
+
+// Column statistics of the sparse hop: reduce `prows` partial rows.
+geer_status launch_colstat(geer_graph *g, const uint64_t *mask, int prows, hipStream_t st)
+{
+    Workspace &ws = g->ws;
+    double *p_m1 = ws.part.as<double>();
+    double *p_m2 = p_m1 + (size_t)prows * kCols;
+    int64_t *p_sd = reinterpret_cast<int64_t *>(p_m2 + (size_t)prows * kCols);
+    double *cs_m1 = ws.colstat.as<double>();
+    double *cs_m2 = cs_m1 + kCols;
+    int64_t *cs_sd = reinterpret_cast<int64_t *>(cs_m2 + kCols);
+    int t2 = prof_begin(g, st);
+    hipLaunchKernelGGL(k_colstat_reduce, dim3(kCols), dim3(256), 0, st, p_m1, p_m2, p_sd, prows,
+                       mask, cs_m1, cs_m2, cs_sd);
+    prof_end(g, t2, PK_COLSTAT, 0.0, 0.0, st);
+    GEER_HIP(hipGetLastError());
+    return GEER_OK;
+}
+
+// Fill a buffer with zeros (a kernel, so it can live inside captured graphs).
+__global__ void k_zero_words(uint4 *__restrict__ p, size_t n16)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = make_uint4(0, 0, 0, 0);
+}
+
+geer_status launch_zero(geer_graph *g, void *p, size_t bytes, hipStream_t st)
+{
+    if (bytes % 16 != 0) return fail(GEER_E_INVALID_ARG, "zero fill needs 16-byte multiples");
+    const size_t n16 = bytes / 16;
+    const int blocks = (int)std::min<size_t>((n16 + 255) / 256, (size_t)g->num_cus * 16);
+    hipLaunchKernelGGL(k_zero_words, dim3(std::max(blocks, 1)), dim3(256), 0, st, (uint4 *)p, n16);
     GEER_HIP(hipGetLastError());
     return GEER_OK;
 }

@@ -225,3 +225,20 @@ def test_geer_deterministic_and_device_entry(cl_graph):
         G.geer_query_device(gg.handle, ds, dt, de, dr, G.geer_params_default(seed=77))
         torch.cuda.synchronize()
         assert np.array_equal(dr.cpu().numpy(), r1)
+
+
+def test_geer_slot_reuse_and_repeat_calls_identical(cl_graph):
+    # groups of 1 or 3 batches reuse the same vector slots many times within
+    # a call; results and schedules must equal a call where nothing is reused
+    g, lam = cl_graph
+    s, t = I.uniform_pairs(g.n, 700, 14)
+    with _graph(g, lam) as gg:
+        outs = []
+        for grp in (16, 1, 3, 16):
+            p = G.geer_params_default(seed=21, group_batches=grp)
+            outs.append(G.geer_query(gg.handle, s, t, 0.05, p, stats=True))
+    r0, st0 = outs[0]
+    for r, st in outs[1:]:
+        assert np.array_equal(st["ell_b"], st0["ell_b"])
+        assert np.array_equal(st["supp_sum"], st0["supp_sum"])
+        assert np.array_equal(r, r0)
