@@ -35,7 +35,7 @@ __global__ __launch_bounds__(1024) void k_amc_plan(QState qs, int64_t q0, int nq
     const int a = min(nq, tid * per), b = min(nq, a + per);
     int64_t local = 0;
     for (int i = a; i < b; ++i) {
-        int64_t q = q0 + i;
+        int64_t q = qs.ord[q0 + i];
         if (qs.active_amc[q]) {
             int64_t eta = qs.eta1[q] << round;
             if (eta >= (int64_t(1) << 32)) *overflow = 1;
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(1024) void k_amc_plan(QState qs, int64_t q0, int nq
     int64_t run = s_sum[tid] - local;  // exclusive prefix of this thread's range
     for (int i = a; i < b; ++i) {
         chunk_off[i] = run;
-        int64_t q = q0 + i;
+        int64_t q = qs.ord[q0 + i];
         if (qs.active_amc[q]) {
             int64_t eta = qs.eta1[q] << round;
             run += (eta + kPairsPerChunk - 1) / kPairsPerChunk;
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_walk(QState qs, int64_t q0, int nq, int
             if (chunk_off[mid] <= c) lo = mid;
             else hi = mid;
         }
-        const int64_t q = q0 + lo;
+        const int64_t q = qs.ord[q0 + lo];
         const int64_t eta = qs.eta1[q] << round;
         const int64_t k = (c - chunk_off[lo]) * kPairsPerChunk + (lane >> 1);
         const bool valid = k < eta;
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(256) void k_amc_stop(QState qs, int64_t q0, int nq,
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= nq) return;
-    const int64_t q = q0 + i;
+    const int64_t q = qs.ord[q0 + i];
     if (!qs.active_amc[q]) return;
     double zs = 0.0, z2 = 0.0;
     for (int64_t c = chunk_off[i] + lane; c < chunk_off[i + 1]; c += 64) {

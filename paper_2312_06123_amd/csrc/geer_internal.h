@@ -61,6 +61,7 @@ struct DevBuf {
 struct QState {
     int32_t *s, *t, *ell, *lb, *lb_target, *lf, *batches, *stop, *active_smm, *active_amc,
         *fallback, *tau_q;
+    int32_t *ord;  // batch position -> query index (batches take consecutive positions)
     int64_t *eta1, *walk_pairs, *supp_sum, *vec_off;
     double *eps, *rb, *psi, *eta_star, *zsum, *z2sum, *var, *f, *rf, *r;
 };
@@ -77,6 +78,7 @@ struct Workspace {
     DevBuf misc;      // small scalars (active masks, totals)
     DevBuf io;        // staging for host inputs/outputs
     DevBuf acc;       // sparse hop: n x kCols fixed-point accumulators (kept all zero)
+    DevBuf meta;      // per-slot masks (active, hop-2 cleanup, hop-2 paths, static levels)
     bool acc_zeroed = false;
     std::vector<char> a_dirty;  // per slot: buffer A was written by a dense hop
     int slots = 0;
@@ -148,6 +150,8 @@ struct geer_graph {
     int32_t n_seg = 0;
     int64_t nnz_heavy = 0;                 // CSR entries in heavy rows
     int fx_shift = 40;                     // fixed-point scale 2^F of the sparse hop
+    std::vector<int32_t> h_row_ptr;        // host copy of the row offsets
+    std::vector<int64_t> h_nbr_work;       // sum of neighbour degrees (= sparse hop-2 work)
     geer::Workspace ws;
     geer::Profiler prof;
 };
@@ -251,6 +255,7 @@ struct QueryCtx {
     int32_t tau, schedule;
     uint64_t seed;
     int64_t qid_offset;
+    hipStream_t stream;
 };
 
 geer_status launch_init_queries(geer_graph *g, const QueryCtx &c, const int32_t *d_fixed,

@@ -165,6 +165,13 @@ static geer_status build_graph(geer_graph *g, const int32_t *rp, const int32_t *
         invf[v] = (float)invd[v];
     }
     g->max_deg = maxd;
+    g->h_row_ptr.assign(rp, rp + n + 1);
+    g->h_nbr_work.assign(n, 0);
+    for (int32_t v = 0; v < n; ++v) {
+        int64_t w = 0;
+        for (int32_t e = rp[v]; e < rp[v + 1]; ++e) w += rp[ci[e] + 1] - rp[ci[e]];
+        g->h_nbr_work[v] = w;
+    }
     // sparse-hop fixed point: a sum of at most max_deg terms, each <= 1, must fit 62 bits
     int bits = 0;
     while ((1ll << bits) <= (long long)maxd) ++bits;
@@ -260,7 +267,7 @@ void geer_graph_destroy(geer_graph *g)
         if (p) (void)hipFree(p);
     DevBuf *bufs[] = {&g->ws.pool,    &g->ws.bits,   &g->ws.part,      &g->ws.segbuf,
                       &g->ws.colstat, &g->ws.qstate, &g->ws.chunk_off, &g->ws.zpart,
-                      &g->ws.misc,    &g->ws.io,     &g->ws.acc};
+                      &g->ws.misc,    &g->ws.io,     &g->ws.acc,       &g->ws.meta};
     for (DevBuf *b : bufs) b->release();
     for (ProfRec &r : g->prof.recs) {
         (void)hipEventDestroy(r.a);

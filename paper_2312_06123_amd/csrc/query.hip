@@ -16,7 +16,7 @@ geer_status ensure_qstate(geer_graph *g, int64_t nq, QState *qs)
 {
     Workspace &ws = g->ws;
     const int64_t cap = std::max<int64_t>(nq, 1);
-    const size_t per = 12 * sizeof(int32_t) + 4 * sizeof(int64_t) + 10 * sizeof(double);
+    const size_t per = 13 * sizeof(int32_t) + 4 * sizeof(int64_t) + 10 * sizeof(double);
     GEER_TRY(ws.qstate.reserve((size_t)cap * per + 64));
     GEER_TRY(ws.misc.reserve((kMiscWords + 1024) * sizeof(int64_t)));
     GEER_TRY(ws.colstat.reserve(kCols * (2 * sizeof(double) + sizeof(int64_t))));
@@ -52,6 +52,7 @@ geer_status ensure_qstate(geer_graph *g, int64_t nq, QState *qs)
     take(qs->active_amc, 4);
     take(qs->fallback, 4);
     take(qs->tau_q, 4);
+    take(qs->ord, 4);
     ws.nq_cap = cap;
     return GEER_OK;
 }
@@ -80,7 +81,7 @@ geer_status ensure_slots(geer_graph *g, int slots, int value_size)
 __global__ void k_batch_mask(QState qs, int64_t q0, int nb, uint64_t *mask)
 {
     const int j = threadIdx.x;
-    bool a = j < nb && qs.active_smm[q0 + j];
+    bool a = j < nb && qs.active_smm[qs.ord[q0 + j]];
     unsigned long long m = __ballot(a);
     if (j == 0) *mask = m;
 }
@@ -119,117 +120,186 @@ struct BatchRec {
     uint64_t hop2_sparse = 0;   // pairs whose hop-2 vectors were pushed into A
 };
 
-// SMM of one batch (pairs q0 .. q0+nb-1) in slot `slot`: hop 1 scatter, hop 2
-// as a sparse push when its work is small, then dense hops until every pair
-// of the batch has stopped.
-static geer_status smm_batch(geer_graph *g, const QueryCtx &c, const SlotView &sv, int slot,
-                             int64_t q0, int nb, int col_tile, int max_hops, hipStream_t st,
-                             int *hops_done, BatchRec *rec)
+// Per-slot device words: [0,G) active mask, [G,2G) hop-2 cleanup mask,
+// [2G,6G) hop-2 path masks (4 words per slot), [6G, 6G + G*L) static level masks.
+struct SlotMeta {
+    uint64_t *base;
+    int G;
+    uint64_t *active(int k) const { return base + k; }
+    uint64_t *h2(int k) const { return base + G + k; }
+    uint64_t *paths(int k) const { return base + 2 * G + 4 * k; }
+    uint64_t *level(int k, int h, int L) const { return base + 6 * G + (size_t)k * L + h; }
+};
+
+// Host view of one group: which batch sits in which slot and its queries.
+struct GroupPlan {
+    int64_t b0 = 0, nbat = 0;  // first batch and batch count
+    int B = 64;
+};
+
+// One hop (h >= 2) of batch k of the group.  hmask: pairs active at this hop.
+static geer_status launch_level(geer_graph *g, const QueryCtx &c, const SlotView &sv,
+                                const SlotMeta &sm, int k, int64_t q0, int nb, int hop,
+                                uint64_t hmask, const uint64_t *d_mask, uint64_t *d_clear,
+                                const int32_t *h_s, const int32_t *h_t, const int32_t *h_ord,
+                                int col_tile, BatchRec *rec, std::vector<uint64_t> &host_paths_all)
 {
     Workspace &ws = g->ws;
-    uint64_t *d_mask = reinterpret_cast<uint64_t *>(ws.misc.as<int64_t>());
-    uint64_t *d_slot_mask = reinterpret_cast<uint64_t *>(ws.misc.as<int64_t>()) + kMiscWords + slot;
-    static thread_local uint64_t host_paths[4];
-    rec->q0 = q0;
-    rec->nb = nb;
-    rec->hop1 = false;
-    rec->hop2_sparse = 0;
-    hipLaunchKernelGGL(k_batch_mask, dim3(1), dim3(64), 0, st, c.qs, q0, nb, d_mask);
-    GEER_HIP(hipGetLastError());
-    *hops_done = 0;
-    geer_status err = GEER_OK;
-    if (host_mask(g, d_mask, st, &err) == 0) return err;
-    GEER_TRY(launch_hop1(g, c, q0, nb, sv.buf(slot, 0), sv.bw(slot, 0), d_mask, sv.vs, false, st));
-    rec->hop1 = true;
-    GEER_TRY(launch_epilogue(g, c, q0, nb, 1, sv.buf(slot, 0), sv.elem_off(slot, 0), d_mask, sv.vs,
-                             0, st));
-    *hops_done = 1;
-    for (int hop = 2;; ++hop) {
-        int64_t sd[kCols];
-        uint64_t m = 0;
-        if (hop == 2) {
-            // mask and the hop-1 support degree sums (= the push work of hop 2)
-            GEER_HIP(hipMemcpyAsync(sd, (char *)ws.colstat.ptr + 2 * kCols * sizeof(double),
-                                    sizeof(sd), hipMemcpyDeviceToHost, st));
-            GEER_HIP(hipMemcpyAsync(&m, d_mask, sizeof(m), hipMemcpyDeviceToHost, st));
-            GEER_HIP(hipStreamSynchronize(st));
-        } else {
-            m = (uint64_t)host_mask(g, d_mask, st, &err);
-            if (err != GEER_OK) return err;
-        }
-        if (m == 0) break;
-        if (hop > max_hops)
-            return fail(GEER_E_DEVICE, "SMM batch still active after the largest possible l");
-        const int wout = hop % 2 == 0 ? 1 : 2;  // output buffer: A on even hops, B on odd
-        bool sparse = false;
-        uint64_t m_lds[2] = {0, 0}, m_glob[2] = {0, 0};  // per-column path masks
-        if (hop == 2 && sv.vs == 4) {
-            double work = 0.0;
-            for (int c2 = 0; c2 < kCols; ++c2) {
-                if (!((m >> (c2 >> 1)) & 1ull)) continue;
-                work += (double)sd[c2];
-                if (sd[c2] <= kHashLoadMax) m_lds[c2 >> 6] |= 1ull << (c2 & 63);
+    const int wout = hop % 2 == 0 ? 1 : 2;  // output buffer: A on even hops, B on odd
+    bool sparse = false;
+    uint64_t m_lds[2] = {0, 0}, m_glob[2] = {0, 0};
+    if (hop == 2 && sv.vs == 4) {
+        // hop-2 work of a column is the neighbour-degree sum of its start node
+        double work = 0.0;
+        for (int j = 0; j < nb; ++j) {
+            if (!((hmask >> j) & 1ull)) continue;
+            const int32_t q = h_ord[q0 + j];
+            for (int side = 0; side < 2; ++side) {
+                const int c2 = 2 * j + side;
+                const int64_t wk = g->h_nbr_work[side ? h_t[q] : h_s[q]];
+                work += (double)wk;
+                if (wk <= kHashLoadMax) m_lds[c2 >> 6] |= 1ull << (c2 & 63);
                 else m_glob[c2 >> 6] |= 1ull << (c2 & 63);
             }
-            sparse = work <= 2.0 * (double)g->nnz;
         }
-        if (sparse) {
-            if (ws.a_dirty[slot]) {
-                GEER_TRY(launch_zero(g, sv.buf(slot, 1), (size_t)g->n * kCols * sv.vs, st));
-                GEER_TRY(launch_zero(g, sv.bw(slot, 1), (size_t)g->n * kBitWords * 4, st));
-                ws.a_dirty[slot] = 0;
-            }
-            // per-pair path masks live next to the batch mask
-            uint64_t *d_paths = d_mask + 1;  // words 1-2: LDS columns, 3-4: global columns
-            host_paths[0] = m_lds[0];
-            host_paths[1] = m_lds[1];
-            host_paths[2] = m_glob[0];
-            host_paths[3] = m_glob[1];
-            GEER_HIP(hipMemcpyAsync(d_paths, host_paths, 4 * sizeof(uint64_t), hipMemcpyHostToDevice, st));
-            GEER_HIP(hipMemcpyAsync(d_slot_mask, d_mask, sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
-            const size_t part_bytes = (size_t)8 * kCols * (2 * sizeof(double) + sizeof(int64_t));
-            GEER_TRY(ws.part.reserve(std::max(ws.part.bytes, part_bytes)));
-            GEER_TRY(launch_zero(g, ws.part.ptr, part_bytes, st));
-            if (m_lds[0] | m_lds[1])
-                GEER_TRY(launch_hop2_lds(g, c, q0, d_paths, sv.buf(slot, 1), sv.bw(slot, 1), sv.vs, st));
-            if (m_glob[0] | m_glob[1]) {
-                GEER_TRY(launch_hop2_sparse(g, c, q0, d_paths + 2, sv.buf(slot, 1), sv.bw(slot, 1), sv.vs, 0, st));
-                GEER_TRY(launch_hop2_sparse(g, c, q0, d_paths + 2, sv.buf(slot, 1), sv.bw(slot, 1), sv.vs, 1, st));
-            }
-            GEER_TRY(launch_colstat(g, d_mask, 8, st));
-            rec->hop2_sparse = m;
-        } else {
-            const int win = hop == 2 ? 0 : (hop % 2 == 0 ? 2 : 1);  // input buffer
-            HopArgs a;
-            a.in = sv.buf(slot, win);
-            a.out = sv.buf(slot, wout);
-            a.in_bits = sv.bw(slot, win);
-            a.out_bits = sv.bw(slot, wout);
-            a.mask = d_mask;
-            a.host_mask = m;
-            a.col0 = 0;
-            a.col_tile = col_tile;
-            GEER_TRY(launch_hop_dense(g, a, sv.vs, st));
-            if (wout == 1) ws.a_dirty[slot] = 1;
-        }
-        GEER_TRY(launch_epilogue(g, c, q0, nb, hop, sv.buf(slot, wout), sv.elem_off(slot, wout), d_mask,
-                                 sv.vs, 1, st));
-        *hops_done = hop;
+        sparse = work <= 2.0 * (double)g->nnz;
     }
+    if (sparse) {
+        if (ws.a_dirty[k]) {
+            GEER_TRY(launch_zero(g, sv.buf(k, 1), (size_t)g->n * kCols * sv.vs, c.stream));
+            GEER_TRY(launch_zero(g, sv.bw(k, 1), (size_t)g->n * kBitWords * 4, c.stream));
+            ws.a_dirty[k] = 0;
+        }
+        uint64_t *hp = &host_paths_all[4 * (size_t)k];
+        hp[0] = m_lds[0];
+        hp[1] = m_lds[1];
+        hp[2] = m_glob[0];
+        hp[3] = m_glob[1];
+        GEER_HIP(hipMemcpyAsync(sm.paths(k), hp, 4 * sizeof(uint64_t), hipMemcpyHostToDevice, c.stream));
+        GEER_HIP(hipMemcpyAsync(sm.h2(k), d_mask, sizeof(uint64_t), hipMemcpyDeviceToDevice, c.stream));
+        const size_t part_bytes = (size_t)8 * kCols * (2 * sizeof(double) + sizeof(int64_t));
+        GEER_TRY(ws.part.reserve(std::max(ws.part.bytes, part_bytes)));
+        GEER_TRY(launch_zero(g, ws.part.ptr, part_bytes, c.stream));
+        if (m_lds[0] | m_lds[1])
+            GEER_TRY(launch_hop2_lds(g, c, q0, sm.paths(k), sv.buf(k, 1), sv.bw(k, 1), sv.vs, c.stream));
+        if (m_glob[0] | m_glob[1]) {
+            GEER_TRY(launch_hop2_sparse(g, c, q0, sm.paths(k) + 2, sv.buf(k, 1), sv.bw(k, 1), sv.vs, 0, c.stream));
+            GEER_TRY(launch_hop2_sparse(g, c, q0, sm.paths(k) + 2, sv.buf(k, 1), sv.bw(k, 1), sv.vs, 1, c.stream));
+        }
+        GEER_TRY(launch_colstat(g, d_mask, 8, c.stream));
+        rec->hop2_sparse = hmask;
+    } else {
+        const int win = hop == 2 ? 0 : (hop % 2 == 0 ? 2 : 1);
+        HopArgs a;
+        a.in = sv.buf(k, win);
+        a.out = sv.buf(k, wout);
+        a.in_bits = sv.bw(k, win);
+        a.out_bits = sv.bw(k, wout);
+        a.mask = d_mask;
+        a.host_mask = hmask;
+        a.col0 = 0;
+        a.col_tile = col_tile;
+        GEER_TRY(launch_hop_dense(g, a, sv.vs, c.stream));
+        if (wout == 1) ws.a_dirty[k] = 1;
+    }
+    GEER_TRY(launch_epilogue(g, c, q0, nb, hop, sv.buf(k, wout), sv.elem_off(k, wout), d_clear, sv.vs,
+                             1, c.stream));
     return GEER_OK;
 }
 
 // Restore H1 and the sparse part of A of a finished batch to zero.
-static geer_status cleanup_batch(geer_graph *g, const QueryCtx &c, const SlotView &sv, int slot,
-                                 const BatchRec &rec, hipStream_t st)
+static geer_status cleanup_batch(geer_graph *g, const QueryCtx &c, const SlotView &sv,
+                                 const SlotMeta &sm, int k, const BatchRec &rec)
 {
     if (rec.hop1)
-        GEER_TRY(launch_hop1(g, c, rec.q0, rec.nb, sv.buf(slot, 0), sv.bw(slot, 0), nullptr, sv.vs,
-                             true, st));
-    if (rec.hop2_sparse && !g->ws.a_dirty[slot]) {
-        uint64_t *d_slot_mask = reinterpret_cast<uint64_t *>(g->ws.misc.as<int64_t>()) + kMiscWords + slot;
-        GEER_TRY(launch_hop2_sparse(g, c, rec.q0, d_slot_mask, sv.buf(slot, 1), sv.bw(slot, 1), sv.vs,
-                                    2, st));
+        GEER_TRY(launch_hop1(g, c, rec.q0, rec.nb, sv.buf(k, 0), sv.bw(k, 0), nullptr, sv.vs, true,
+                             c.stream));
+    if (rec.hop2_sparse && !g->ws.a_dirty[k])
+        GEER_TRY(launch_hop2_sparse(g, c, rec.q0, sm.h2(k), sv.buf(k, 1), sv.bw(k, 1), sv.vs, 2,
+                                    c.stream));
+    return GEER_OK;
+}
+
+// SMM of a group of batches.  Greedy: level-synchronous, one host read of the
+// batch masks per hop level.  Static (fixed / learned depths known on the
+// host): the whole launch sequence is fixed in advance, no host reads.
+static geer_status smm_group(geer_graph *g, const QueryCtx &c, const SlotView &sv,
+                             const SlotMeta &sm, const GroupPlan &gp, bool is_static,
+                             const int32_t *h_target, const int32_t *h_s, const int32_t *h_t,
+                             const int32_t *h_ord, int col_tile, int max_hops,
+                             std::vector<BatchRec> &recs)
+{
+    const int G = (int)gp.nbat;
+    std::vector<uint64_t> hm(G, 0), host_paths(4 * (size_t)sm.G, 0);
+    std::vector<int64_t> q0s(G);
+    std::vector<int> nbs(G);
+    int levels = 0;
+    for (int k = 0; k < G; ++k) {
+        q0s[k] = (gp.b0 + k) * gp.B;
+        nbs[k] = (int)std::min<int64_t>(gp.B, c.nq - q0s[k]);
+        recs[k] = BatchRec();
+        recs[k].q0 = q0s[k];
+        recs[k].nb = nbs[k];
+    }
+    if (is_static) {
+        // level masks from the known depths
+        int L = 1;
+        for (int k = 0; k < G; ++k)
+            for (int j = 0; j < nbs[k]; ++j) L = std::max(L, h_target[h_ord[q0s[k] + j]] + 1);
+        levels = L;
+        std::vector<uint64_t> lv((size_t)G * L, 0);
+        for (int k = 0; k < G; ++k)
+            for (int j = 0; j < nbs[k]; ++j) {
+                const int t = h_target[h_ord[q0s[k] + j]];
+                for (int h = 1; h <= t && h < L; ++h) lv[(size_t)k * L + h] |= 1ull << j;
+            }
+        GEER_TRY(g->ws.meta.reserve(std::max(g->ws.meta.bytes, (6 * (size_t)sm.G + (size_t)G * L) * 8)));
+        SlotMeta sml{g->ws.meta.as<uint64_t>(), sm.G};
+        GEER_HIP(hipMemcpyAsync(sml.level(0, 0, L), lv.data(), lv.size() * 8, hipMemcpyHostToDevice,
+                                c.stream));
+        for (int k = 0; k < G; ++k) {
+            const uint64_t m1 = lv[(size_t)k * L + (L > 1 ? 1 : 0)];
+            if (L < 2 || m1 == 0) continue;
+            GEER_TRY(launch_hop1(g, c, q0s[k], nbs[k], sv.buf(k, 0), sv.bw(k, 0), nullptr, sv.vs, false,
+                                 c.stream));
+            recs[k].hop1 = true;
+            GEER_TRY(launch_epilogue(g, c, q0s[k], nbs[k], 1, sv.buf(k, 0), sv.elem_off(k, 0),
+                                     sml.active(k), sv.vs, 0, c.stream));
+        }
+        for (int h = 2; h < L; ++h)
+            for (int k = 0; k < G; ++k) {
+                const uint64_t mh = lv[(size_t)k * L + h];
+                if (!mh) continue;
+                GEER_TRY(launch_level(g, c, sv, sml, k, q0s[k], nbs[k], h, mh, sml.level(k, h, L),
+                                      sml.active(k), h_s, h_t, h_ord, col_tile, &recs[k], host_paths));
+            }
+        (void)levels;
+        return GEER_OK;
+    }
+    // greedy: level 1 for every batch, then one read of all masks per level
+    for (int k = 0; k < G; ++k) {
+        hipLaunchKernelGGL(k_batch_mask, dim3(1), dim3(64), 0, c.stream, c.qs, q0s[k], nbs[k], sm.active(k));
+        GEER_HIP(hipGetLastError());
+        GEER_TRY(launch_hop1(g, c, q0s[k], nbs[k], sv.buf(k, 0), sv.bw(k, 0), nullptr, sv.vs, false,
+                             c.stream));
+        recs[k].hop1 = true;
+        GEER_TRY(launch_epilogue(g, c, q0s[k], nbs[k], 1, sv.buf(k, 0), sv.elem_off(k, 0), sm.active(k),
+                                 sv.vs, 0, c.stream));
+    }
+    for (int hop = 2;; ++hop) {
+        GEER_HIP(hipMemcpyAsync(hm.data(), sm.active(0), G * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                                c.stream));
+        GEER_HIP(hipStreamSynchronize(c.stream));
+        bool any = false;
+        for (int k = 0; k < G; ++k) any |= hm[k] != 0;
+        if (!any) break;
+        if (hop > max_hops)
+            return fail(GEER_E_DEVICE, "SMM batch still active after the largest possible l");
+        for (int k = 0; k < G; ++k) {
+            if (!hm[k]) continue;
+            GEER_TRY(launch_level(g, c, sv, sm, k, q0s[k], nbs[k], hop, hm[k], sm.active(k), sm.active(k),
+                                  h_s, h_t, h_ord, col_tile, &recs[k], host_paths));
+        }
     }
     return GEER_OK;
 }
@@ -268,8 +338,10 @@ static geer_status check_params(const geer_params &p)
 }
 
 // The whole query pipeline on device-resident inputs (already in qstate).
+// h_s / h_t: host copies of the pairs (used for planning only).
 static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
-                               const int32_t *d_fixed, double min_eps, hipStream_t st)
+                               const int32_t *d_fixed, double min_eps, const int32_t *h_s,
+                               const int32_t *h_t)
 {
     // no pair can need more products than l of Eq. (ell) at d(s) = d(t) = 1
     const int max_hops = ell_of(1.0, 1.0, min_eps, c.lambda);
@@ -279,27 +351,44 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
     const int G = std::min(1024, p.group_batches ? p.group_batches : default_group_batches(g, vs, nbatches));
     const int col_tile = p.col_tile ? p.col_tile : default_col_tile(g, vs);
     GEER_TRY(ensure_slots(g, G, vs));
-    GEER_TRY(launch_init_queries(g, c, d_fixed, -1, st));
+    GEER_TRY(g->ws.meta.reserve((6 * (size_t)G + (size_t)G * (max_hops + 2)) * 8 + 64));
+    GEER_TRY(launch_init_queries(g, c, d_fixed, -1, c.stream));
+    const bool is_static = p.schedule != GEER_SCHEDULE_GREEDY;
+    std::vector<int32_t> ord(c.nq), target;
+    for (int64_t i = 0; i < c.nq; ++i) ord[i] = (int32_t)i;
+    if (is_static) {
+        // depths are known: bucket pairs of equal SMM depth into the same
+        // batches so that dense hops run on full batches
+        target.resize(c.nq);
+        GEER_HIP(hipMemcpyAsync(target.data(), c.qs.lb_target, c.nq * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, c.stream));
+        std::vector<int32_t> ellh(c.nq), act(c.nq);
+        GEER_HIP(hipMemcpyAsync(ellh.data(), c.qs.ell, c.nq * sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+        GEER_HIP(hipMemcpyAsync(act.data(), c.qs.active_smm, c.nq * sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+        GEER_HIP(hipStreamSynchronize(c.stream));
+        for (int64_t i = 0; i < c.nq; ++i) target[i] = act[i] ? std::min(target[i], ellh[i]) : 0;
+        std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return target[a] > target[b]; });
+    }
+    GEER_HIP(hipMemcpyAsync(c.qs.ord, ord.data(), c.nq * sizeof(int32_t), hipMemcpyHostToDevice, c.stream));
     SlotView sv{g->ws.pool.as<char>(), g->ws.bits.as<uint32_t>(), (size_t)g->n, vs};
+    SlotMeta sm{g->ws.meta.as<uint64_t>(), G};
+    std::vector<BatchRec> recs(G);
     for (int64_t b0 = 0; b0 < nbatches; b0 += G) {
-        const int64_t b1 = std::min<int64_t>(nbatches, b0 + G);
-        std::vector<BatchRec> recs((size_t)(b1 - b0));
-        for (int64_t b = b0; b < b1; ++b) {
-            const int64_t q0 = b * B;
-            const int nb = (int)std::min<int64_t>(B, c.nq - q0);
-            int hops = 0;
-            GEER_TRY(smm_batch(g, c, sv, (int)(b - b0), q0, nb, col_tile, max_hops, st, &hops,
-                               &recs[(size_t)(b - b0)]));
-        }
+        GroupPlan gp;
+        gp.b0 = b0;
+        gp.nbat = std::min<int64_t>(nbatches, b0 + G) - b0;
+        gp.B = B;
+        sm.base = g->ws.meta.as<uint64_t>();
+        GEER_TRY(smm_group(g, c, sv, sm, gp, is_static, target.data(), h_s, h_t, ord.data(), col_tile,
+                           max_hops, recs));
+        sm.base = g->ws.meta.as<uint64_t>();
         AmcGroup grp;
         grp.q0 = b0 * B;
-        grp.nq = std::min<int64_t>(c.nq, b1 * B) - grp.q0;
+        grp.nq = std::min<int64_t>(c.nq, (b0 + gp.nbat) * B) - grp.q0;
         grp.pool = sv.pool;
         grp.value_size = vs;
-        GEER_TRY(amc_phase(g, c, grp, st, p.walk_ilp));
-        // restore the group's sparse buffers to all-zero
-        for (int64_t b = b0; b < b1; ++b)
-            GEER_TRY(cleanup_batch(g, c, sv, (int)(b - b0), recs[(size_t)(b - b0)], st));
+        GEER_TRY(amc_phase(g, c, grp, c.stream, p.walk_ilp));
+        for (int k = 0; k < gp.nbat; ++k) GEER_TRY(cleanup_batch(g, c, sv, sm, k, recs[k]));
     }
     return GEER_OK;
 }
@@ -373,7 +462,8 @@ geer_status geer_query(geer_graph *g, int64_t nq, const int32_t *s, const int32_
         GEER_HIP(hipMemcpyAsync(d_fixed, p.fixed_ell_b, nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
     double min_eps = eps[0];
     for (int64_t i = 1; i < nq; ++i) min_eps = std::min(min_eps, eps[i]);
-    GEER_TRY(run_queries(g, c, p, d_fixed, min_eps, st));
+    c.stream = st;
+    GEER_TRY(run_queries(g, c, p, d_fixed, min_eps, s, t));
     GEER_TRY(launch_finalize(g, c, d_r, stats ? d_stats : nullptr, st));
     GEER_HIP(hipMemcpyAsync(r_out, d_r, nq * sizeof(double), hipMemcpyDeviceToHost, st));
     if (stats)
@@ -427,12 +517,21 @@ geer_status geer_query_device(geer_graph *g, int64_t nq, const int32_t *d_s, con
     if (p.schedule == GEER_SCHEDULE_FIXED)
         GEER_HIP(hipMemcpyAsync(d_fixed, p.fixed_ell_b, nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
     std::vector<double> heps(nq);
+    std::vector<int32_t> hs(nq), ht(nq);
     GEER_HIP(hipMemcpyAsync(heps.data(), d_eps, nq * sizeof(double), hipMemcpyDeviceToHost, st));
+    GEER_HIP(hipMemcpyAsync(hs.data(), d_s, nq * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GEER_HIP(hipMemcpyAsync(ht.data(), d_t, nq * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     GEER_HIP(hipStreamSynchronize(st));
     double min_eps = 1e300;
     for (double e : heps)
         if (e > 0.0 && e < min_eps) min_eps = e;
-    GEER_TRY(run_queries(g, c, p, d_fixed, min_eps, st));
+    // out-of-range ids are reported after the run; plan with clamped copies
+    for (int64_t i = 0; i < nq; ++i) {
+        hs[i] = std::min(std::max(hs[i], 0), g->n - 1);
+        ht[i] = std::min(std::max(ht[i], 0), g->n - 1);
+    }
+    c.stream = st;
+    GEER_TRY(run_queries(g, c, p, d_fixed, min_eps, hs.data(), ht.data()));
     GEER_TRY(launch_finalize(g, c, d_r_out, d_stats, st));
     GEER_HIP(hipStreamSynchronize(st));
     // invalid entries were turned into NaN results by the init kernel
@@ -477,9 +576,21 @@ geer_status geer_smm(geer_graph *g, int32_t nq, const int32_t *s, const int32_t 
     GEER_TRY(launch_init_queries(g, c, nullptr, hops, st));
     SlotView sv{g->ws.pool.as<char>(), g->ws.bits.as<uint32_t>(), (size_t)g->n, vs};
     const int tile = col_tile ? col_tile : default_col_tile(g, vs);
-    int done = 0;
-    BatchRec rec;
-    if (hops > 0) GEER_TRY(smm_batch(g, c, sv, 0, 0, nq, tile, hops, st, &done, &rec));
+    c.stream = st;
+    std::vector<int32_t> ord(nq), target(nq, hops);
+    for (int i = 0; i < nq; ++i) ord[i] = i;
+    GEER_HIP(hipMemcpyAsync(c.qs.ord, ord.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    const int G1 = std::max(1, g->ws.slots);
+    GEER_TRY(g->ws.meta.reserve((6 * (size_t)G1 + (size_t)G1 * (hops + 2)) * 8 + 64));
+    SlotMeta sm{g->ws.meta.as<uint64_t>(), G1};
+    std::vector<BatchRec> recs(1);
+    if (hops > 0) {
+        GroupPlan gp;
+        gp.b0 = 0;
+        gp.nbat = 1;
+        gp.B = nq;
+        GEER_TRY(smm_group(g, c, sv, sm, gp, true, target.data(), s, t, ord.data(), tile, hops, recs));
+    }
     GEER_HIP(hipStreamSynchronize(st));
     const size_t n = (size_t)g->n;
     if (hops == 0) {
@@ -537,7 +648,7 @@ geer_status geer_smm(geer_graph *g, int32_t nq, const int32_t *s, const int32_t 
     }
     // restore the sparse buffers to zero
     if (hops > 0) {
-        GEER_TRY(cleanup_batch(g, c, sv, 0, rec, st));
+        GEER_TRY(cleanup_batch(g, c, sv, sm, 0, recs[0]));
         GEER_HIP(hipStreamSynchronize(st));
     }
     return GEER_OK;
@@ -656,8 +767,11 @@ extern "C" geer_status geer_amc(geer_graph *g, int32_t s, int32_t t, const doubl
     GEER_HIP(hipMemcpy2D(sv.buf(0, 1), (size_t)kCols * vs, host.data(), (size_t)2 * vs, (size_t)2 * vs,
                          (size_t)n, hipMemcpyHostToDevice));
     g->ws.a_dirty[0] = 1;  // A now holds dense caller vectors
+    c.stream = st;
+    const int32_t zero = 0;
     GEER_HIP(hipMemcpyAsync(c.qs.s, &s, sizeof(int32_t), hipMemcpyHostToDevice, st));
     GEER_HIP(hipMemcpyAsync(c.qs.t, &t, sizeof(int32_t), hipMemcpyHostToDevice, st));
+    GEER_HIP(hipMemcpyAsync(c.qs.ord, &zero, sizeof(int32_t), hipMemcpyHostToDevice, st));
     GEER_TRY(launch_column_top2(g, sv.buf(0, 1), 2, vs, st));
     double *cs_m1 = g->ws.colstat.as<double>();
     hipLaunchKernelGGL(k_amc_setup, dim3(1), dim3(1), 0, st, c.qs, g->d_row_ptr, lf, eps, tau, delta,

@@ -144,7 +144,7 @@ __global__ __launch_bounds__(64) void k_hop1(QState qs, int64_t q0,
 {
     const int c = blockIdx.x;  // column within the batch
     const int j = c >> 1, side = c & 1;
-    const int64_t q = q0 + j;
+    const int64_t q = qs.ord[q0 + j];
     const int lane = threadIdx.x;
     if (!clear && !qs.active_smm[q]) return;
     if (clear && qs.lb[q] < 1) return;  // hop 1 never ran for this pair
@@ -688,7 +688,7 @@ __global__ void k_epilogue(QState qs, int64_t q0, int nb, int hop, const T *__re
 {
     const int j = threadIdx.x;
     if (j >= nb) return;
-    const int64_t q = q0 + j;
+    const int64_t q = qs.ord[q0 + j];
     if (!qs.active_smm[q]) return;
     const int32_t s = qs.s[q], t = qs.t[q];
     const double ids = 1.0 / (row_ptr[s + 1] - row_ptr[s]);
@@ -850,7 +850,7 @@ __global__ __launch_bounds__(256) void k_hop2_sparse(
     T m1 = 0, m2 = 0;
     int64_t sd = 0;
     if (act) {
-        const int64_t q = q0 + j;
+        const int64_t q = qs.ord[q0 + j];
         const int32_t u = (c & 1) ? qs.t[q] : qs.s[q];
         const int32_t b0 = row_ptr[u], du = row_ptr[u + 1] - b0;
         const uint32_t bit = 1u << (c & 31);
@@ -980,7 +980,7 @@ __global__ __launch_bounds__(512) void k_hop2_lds(
             s_key[i] = -1;
             s_val[i] = 0ull;
         }
-        const int64_t q = q0 + j;
+        const int64_t q = qs.ord[q0 + j];
         const int32_t u = (c & 1) ? qs.t[q] : qs.s[q];
         const int32_t b0 = row_ptr[u], du = row_ptr[u + 1] - b0;
         __syncthreads();

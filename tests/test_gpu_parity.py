@@ -242,3 +242,23 @@ def test_geer_slot_reuse_and_repeat_calls_identical(cl_graph):
         assert np.array_equal(st["ell_b"], st0["ell_b"])
         assert np.array_equal(st["supp_sum"], st0["supp_sum"])
         assert np.array_equal(r, r0)
+
+
+def test_geer_mixed_fixed_depths_bucketed(cl_graph):
+    # per-pair depths 0..4: pairs are regrouped into batches by depth; every
+    # result must still equal the checker run with the same per-pair depth
+    g, lam = cl_graph
+    s, t = I.uniform_pairs(g.n, 333, 15)
+    lb = np.random.default_rng(16).integers(0, 5, len(s)).astype(np.int32)
+    with _graph(g, lam) as gg:
+        r, st = G.geer_query(gg.handle, s, t, 0.1, G.geer_params_default(seed=31), stats=True,
+                             fixed_ell_b=lb)
+    ro, sto = oracle.geer(g.row_ptr, g.col_idx, s, t, 0.1, lam, seed=31, schedule="fixed",
+                          fixed_lb=lb)
+    assert np.array_equal(st["ell_b"], np.minimum(lb, st["ell"]))
+    assert np.array_equal(st["ell_b"], sto["ell_b"])
+    agree = _stats_agree(st, sto)
+    assert agree.mean() >= 0.95
+    assert np.all(np.abs(r[agree] - ro[agree]) <= 1e-5 * np.maximum(1.0, np.abs(ro[agree])))
+    ex, _ = oracle.exact_cg(g.row_ptr, g.col_idx, s, t)
+    assert np.mean(np.abs(r - ex) <= 0.1) >= 0.99
