@@ -198,6 +198,85 @@ geer_status geer_amc(geer_graph *g, int32_t s, int32_t t, const double *x, const
                      double eps, int32_t lf, int32_t tau, double delta, uint64_t seed, uint32_t q,
                      uint32_t flags, double *rf_out, geer_query_stats *stats);
 
+/* ---- Learned scheduler ------------------------------------------------- */
+
+/* A 3-layer MLP (GEER_MLP_FEATURES -> 64 -> 64 -> 3, ReLU) that predicts, per
+ * pair, the SMM depth l_b, the AMC batch count tau and log10 of the absolute
+ * error.  Used by GEER_SCHEDULE_LEARNED; pairs whose predicted error exceeds
+ * eps or whose features leave the training range use the greedy switch of
+ * Eq. (smm-amc).  The estimator (l, eta*, the stop rule, delta) is unchanged,
+ * so the guarantee of Theorem 3.2 holds for any prediction.
+ * Parameters: FP32 master copy, BF16 copy for inference; layout row-major
+ * W1[F][64], b1[64], W2[64][64], b2[64], W3[64][3], b3[3].
+ * Features (raw, per pair): log2 d(s), log2 d(t), l/16, log2(1 + sum of the
+ * neighbour degrees of s), same for t, log2 of the smallest neighbour degree
+ * of s, same for t, edge(s,t), log2(1 + common neighbours),
+ * log2(1/(1-lambda)), log2 eps, log2 rho2, log2 rhod (cost ratios of the
+ * graph, geer_graph_set_costs). */
+#define GEER_MLP_FEATURES 13
+#define GEER_MLP_HIDDEN 64
+#define GEER_MLP_OUTPUTS 3
+#define GEER_MLP_PARAMS (13 * 64 + 64 + 64 * 64 + 64 + 64 * 3 + 3)
+
+/* New model with He-uniform weights from `seed` (host memory; device copies
+ * are made on first use on the current device). */
+geer_status geer_model_create(uint64_t seed, geer_model **out);
+void geer_model_free(geer_model *m);
+/* Checkpoint: weights, Adam moments, step count, seed and feature
+ * normalisation; training resumes from a loaded model. */
+geer_status geer_model_save(const geer_model *m, const char *path);
+geer_status geer_model_load(const char *path, geer_model **out);
+/* count must be GEER_MLP_PARAMS.  set_params resets the optimiser state. */
+geer_status geer_model_get_params(const geer_model *m, float *out, int64_t count);
+geer_status geer_model_set_params(geer_model *m, const float *in, int64_t count);
+/* Feature normalisation z = (x - mean) / stdev and the training range [lo, hi]
+ * (host float[GEER_MLP_FEATURES] each). */
+geer_status geer_model_set_norm(geer_model *m, const float *mean, const float *stdev,
+                                const float *lo, const float *hi);
+/* Cost ratios used as features: rho2 = cost of one unit of hop-2 push work,
+ * rhod = cost of one dense hop of a 64-pair batch divided by 64, both in
+ * units of one walk step (geer_autotune measures them). */
+geer_status geer_graph_set_costs(geer_graph *g, double rho2, double rhod);
+/* Raw features of nq pairs: host float[nq * GEER_MLP_FEATURES]. */
+geer_status geer_features(geer_graph *g, int64_t nq, const int32_t *s, const int32_t *t,
+                          const double *eps, float *feat_out);
+/* Forward pass on normalised inputs x (host float[nb * F]) -> y (host
+ * float[nb * 3]), with the FP32 weights or (use_bf16 != 0) the BF16 copy. */
+geer_status geer_mlp_forward(geer_model *m, int64_t nb, const float *x, int32_t use_bf16,
+                             float *y_out);
+/* Gradient of the weighted squared loss mean_b sum_o w[b,o] (yhat - y)^2 of
+ * one minibatch (nb <= 64) at the current FP32 weights: host float[PARAMS]. */
+geer_status geer_mlp_grad(geer_model *m, int32_t nb, const float *x, const float *y,
+                          const float *w, float *grad_out);
+/* `steps` Adam steps (lr, beta1 0.9, beta2 0.999) on minibatches of `batch`
+ * (<= 64) samples of (x, y, w) (n samples, normalised inputs).  Minibatch
+ * indices come from `order` (host int64[steps * batch]) or, if NULL, from a
+ * counter-based hash of (model seed, step, slot).  loss_out (nullable):
+ * host float[steps], the minibatch loss before each update. */
+geer_status geer_mlp_train(geer_model *m, int64_t n, const float *x, const float *y,
+                           const float *w, int32_t steps, int32_t batch, double lr,
+                           const int64_t *order, float *loss_out);
+
+/* ---- Autotuner ---------------------------------------------------------- */
+
+typedef struct geer_tuning {
+    int32_t col_tile;          /* fastest SpMM column tile (32, 64 or 128) */
+    int32_t from_cache;        /* 1 if read from the cache file */
+    double ns_per_walk_step;   /* measured cost of one walk step */
+    double ns_per_hop2_unit;   /* one unit of sparse hop-2 work (one CSR entry of one column) */
+    double ns_per_dense_hop;   /* one dense hop of a 64-pair batch */
+    double rho2, rhod;         /* the cost ratios stored with geer_graph_set_costs */
+} geer_tuning;
+
+/* Time the SpMM column tiles and measure the unit costs of the phases on a
+ * sample of pairs (host arrays, nq >= 64 recommended; lambda must be set),
+ * then store the best tile (used when geer_params.col_tile == 0) and the
+ * cost ratios in the graph.  cache_path (nullable): a text file keyed by
+ * (n, nnz, max degree, device name); an entry found there is used instead
+ * of measuring, and new measurements are appended. */
+geer_status geer_autotune(geer_graph *g, int64_t nq, const int32_t *s, const int32_t *t,
+                          const double *eps, const char *cache_path, geer_tuning *out);
+
 /* ---- Kernel timing (HIP events on the stream each kernel runs on) ------- */
 
 /* One record per kernel kind: launches, summed event-timed duration, and

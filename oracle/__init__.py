@@ -11,6 +11,8 @@ Parts:
     budget h), walk traces, Algorithm AMC, Algorithm GEER with the greedy
     switch of Eq. (smm-amc) or a fixed depth, the truncated series of
     Eq. (r-ell), and Jacobi-PCG for the exact resistance of Definition 2.1.
+  * ``mlp``: FP64 reference of the learned scheduler's network, its
+    gradients and the Adam update.
   * numpy/LAPACK: the exact resistance from the Laplacian pseudo-inverse
     (Definition 2.1) for small graphs, and lambda = max(|lambda_2|, |lambda_n|)
     of P (Theorem 3.1) by dense eigendecomposition or ARPACK (the paper's own
@@ -91,7 +93,8 @@ def lib():
         L.oracle_geer.argtypes = [ctypes.c_int64, _i64p, _i32p, ctypes.c_int64, _i32p, _i32p,
                                   _f64p, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
                                   ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p,
-                                  ctypes.c_void_p, ctypes.c_int32, _f64p, ctypes.c_void_p]
+                                  ctypes.c_void_p, ctypes.c_int32, _f64p, ctypes.c_void_p,
+                                  ctypes.c_void_p]
         L.oracle_geer.restype = ctypes.c_int
         L.oracle_series.argtypes = [ctypes.c_int64, _i64p, _i32p, ctypes.c_int64, _i32p, _i32p,
                                     _i32p, ctypes.c_int32, _f64p]
@@ -229,7 +232,7 @@ def amc_samples(row_ptr, col_idx, s, t, x, y, lf, seed, q, batch, count) -> np.n
 
 
 def geer(row_ptr, col_idx, s, t, eps, lam, *, tau=5, delta=0.01, seed=0, schedule="greedy",
-         fixed_lb=None, qid=None, threads=None):
+         fixed_lb=None, qid=None, threads=None, tau_per_pair=None):
     """Algorithm GEER for arrays of pairs -> (r', stats record array).
 
     schedule: "greedy" (Eq. smm-amc) or "fixed" (exactly min(fixed_lb, l) SMM
@@ -249,11 +252,15 @@ def geer(row_ptr, col_idx, s, t, eps, lam, *, tau=5, delta=0.01, seed=0, schedul
     elif schedule != "greedy":
         raise ValueError(schedule)
     q = None if qid is None else np.ascontiguousarray(qid, dtype=np.int64)
+    tp = None
+    if tau_per_pair is not None:
+        tp = np.ascontiguousarray(np.broadcast_to(np.asarray(tau_per_pair, dtype=np.int32), (nq,)))
     rc = lib().oracle_geer(rp.size - 1, rp, ci, nq, s, t, e, float(lam), int(tau), float(delta),
                            int(seed), 0 if schedule == "greedy" else 1,
                            None if flb is None else flb.ctypes.data,
                            None if q is None else q.ctypes.data,
-                           int(threads or _default_threads()), out, st.ctypes.data)
+                           int(threads or _default_threads()), out, st.ctypes.data,
+                           None if tp is None else tp.ctypes.data)
     if rc != 0:
         raise MemoryError("oracle_geer failed to allocate")
     return out, st

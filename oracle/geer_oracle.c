@@ -438,6 +438,7 @@ typedef struct {
     double lambda, delta, tol;
     int32_t tau, schedule, max_iter;
     const int32_t *fixed_lb;   /* per query, schedule 1 */
+    const int32_t *tau_arr;    /* per query batch count, or NULL for `tau` */
     const int32_t *ell_in;     /* per query, series */
     uint64_t seed;
     const int64_t *qid;        /* global query index for the walk counter, or NULL */
@@ -469,8 +470,9 @@ static void *worker(void *arg)
             oracle_stats st;
             uint32_t q = (uint32_t)(j->qid ? j->qid[i] : i);
             int32_t flb = j->fixed_lb ? j->fixed_lb[i] : 0;
+            int32_t tq = j->tau_arr ? j->tau_arr[i] : j->tau;
             j->r_out[i] = geer_one(j->n, j->rp, j->ci, j->s[i], j->t[i], j->eps[i], j->lambda,
-                                   j->tau, j->delta, j->seed, q, j->schedule, flb, &w, &st);
+                                   tq, j->delta, j->seed, q, j->schedule, flb, &w, &st);
             if (j->stats) j->stats[i] = st;
         } else if (j->kind == 1) {
             j->r_out[i] = series_one(j->n, j->rp, j->ci, j->s[i], j->t[i], j->ell_in[i], &w);
@@ -508,10 +510,11 @@ int oracle_geer(int64_t n, const int64_t *rp, const int32_t *ci, int64_t nq,
                 const int32_t *s, const int32_t *t, const double *eps, double lambda,
                 int32_t tau, double delta, uint64_t seed, int32_t schedule,
                 const int32_t *fixed_lb, const int64_t *qid, int32_t threads,
-                double *r_out, oracle_stats *stats)
+                double *r_out, oracle_stats *stats, const int32_t *tau_arr)
 {
     job_t j;
     memset(&j, 0, sizeof(j));
+    j.tau_arr = tau_arr;
     j.kind = 0; j.n = n; j.nq = nq; j.rp = rp; j.ci = ci; j.s = s; j.t = t; j.eps = eps;
     j.lambda = lambda; j.tau = tau; j.delta = delta; j.seed = seed; j.schedule = schedule;
     j.fixed_lb = fixed_lb; j.qid = qid; j.r_out = r_out; j.stats = stats;

@@ -171,6 +171,7 @@ __global__ __launch_bounds__(256) void k_amc_stop(QState qs, int64_t q0, int nq,
     const double z = zs / eta;
     double var = z2 / eta - z * z;
     if (var < 0.0) var = 0.0;
+    tau = qs.tau_q[q];
     const double f = bernstein_of(eta, var, qs.psi[q], delta / (double)tau);
     qs.batches[q] = round + 1;
     qs.walk_pairs[q] += qs.eta1[q] << round;

@@ -41,6 +41,7 @@ constexpr int kMaxPairs = kCols / 2;  // pairs per SMM batch
 constexpr int kBitWords = kCols / 32; // support bitmask words per node
 constexpr int kSegNnz = 256;          // rows longer than this are split into segments
 constexpr int kPairsPerChunk = 32;    // walk pairs per wavefront work item (64 lanes)
+constexpr int kLearnedTauMax = 8;     // largest AMC batch count the learned schedule picks
 
 // ----------------------------------------------------------------------------
 // Device-resident growable buffer
@@ -79,6 +80,7 @@ struct Workspace {
     DevBuf io;        // staging for host inputs/outputs
     DevBuf acc;       // sparse hop: n x kCols fixed-point accumulators (kept all zero)
     DevBuf meta;      // per-slot masks (active, hop-2 cleanup, hop-2 paths, static levels)
+    DevBuf feat;      // learned scheduler: per-pair features
     bool acc_zeroed = false;
     std::vector<char> a_dirty;  // per slot: buffer A was written by a dense hop
     int slots = 0;
@@ -101,6 +103,7 @@ enum ProfKind {
     PK_MLP,
     PK_HOP2_SPARSE,
     PK_HOP2_LDS,
+    PK_DENSE_HOP,
     PK_COUNT
 };
 
@@ -151,6 +154,10 @@ struct geer_graph {
     int64_t nnz_heavy = 0;                 // CSR entries in heavy rows
     int fx_shift = 40;                     // fixed-point scale 2^F of the sparse hop
     std::vector<int32_t> h_row_ptr;        // host copy of the row offsets
+    int64_t *d_nbr_work = nullptr;         // per node: sum of neighbour degrees
+    int32_t *d_min_nbr_deg = nullptr;      // per node: smallest neighbour degree
+    double rho2 = 6.0, rhod = 1e6;         // cost ratios (learned-scheduler features)
+    int tuned_col_tile = 0;                // autotuner's SpMM column tile (0: not tuned)
     std::vector<int64_t> h_nbr_work;       // sum of neighbour degrees (= sparse hop-2 work)
     geer::Workspace ws;
     geer::Profiler prof;
@@ -296,6 +303,10 @@ geer_status launch_walk_traces(geer_graph *g, int32_t nw, const int32_t *start, 
 // Profiling helpers (graph.hip): bracket a launch with events when enabled.
 int prof_begin(geer_graph *g, hipStream_t st);
 void prof_end(geer_graph *g, int token, int kind, double bytes, double units, hipStream_t st);
+void prof_add_units(geer_graph *g, int kind, double units);
+
+geer_status launch_learned(geer_graph *g, const QueryCtx &c, const geer_model *m, float *d_feat,
+                           int32_t tau_max, hipStream_t st);
 
 // Workspace helpers (query.hip)
 geer_status ensure_qstate(geer_graph *g, int64_t nq, QState *qs);

@@ -77,6 +77,11 @@ void prof_end(geer_graph *g, int token, int kind, double bytes, double units, hi
     (void)hipEventRecord(r.b, st);
 }
 
+void prof_add_units(geer_graph *g, int kind, double units)
+{
+    if (g->prof.on) g->prof.units[kind] += units;
+}
+
 static geer_status prof_flush(geer_graph *g)
 {
     Profiler &p = g->prof;
@@ -167,11 +172,20 @@ static geer_status build_graph(geer_graph *g, const int32_t *rp, const int32_t *
     g->max_deg = maxd;
     g->h_row_ptr.assign(rp, rp + n + 1);
     g->h_nbr_work.assign(n, 0);
+    std::vector<int32_t> mind(n, 0);
     for (int32_t v = 0; v < n; ++v) {
         int64_t w = 0;
-        for (int32_t e = rp[v]; e < rp[v + 1]; ++e) w += rp[ci[e] + 1] - rp[ci[e]];
+        int32_t md = INT32_MAX;
+        for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+            const int32_t du = rp[ci[e] + 1] - rp[ci[e]];
+            w += du;
+            md = std::min(md, du);
+        }
         g->h_nbr_work[v] = w;
+        mind[v] = md;
     }
+    GEER_TRY(upload(&g->d_nbr_work, g->h_nbr_work.data(), (size_t)n));
+    GEER_TRY(upload(&g->d_min_nbr_deg, mind.data(), (size_t)n));
     // sparse-hop fixed point: a sum of at most max_deg terms, each <= 1, must fit 62 bits
     int bits = 0;
     while ((1ll << bits) <= (long long)maxd) ++bits;
@@ -262,12 +276,13 @@ void geer_graph_destroy(geer_graph *g)
     if (g->stream) (void)hipStreamSynchronize(g->stream);
     void *ptrs[] = {g->d_row_ptr,    g->d_col_idx,    g->d_inv_deg_f,       g->d_inv_deg_d,
                     g->d_light_rows, g->d_heavy_rows, g->d_heavy_seg_start, g->d_seg_begin,
-                    g->d_seg_end};
+                    g->d_seg_end,    g->d_nbr_work,   g->d_min_nbr_deg};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     DevBuf *bufs[] = {&g->ws.pool,    &g->ws.bits,   &g->ws.part,      &g->ws.segbuf,
                       &g->ws.colstat, &g->ws.qstate, &g->ws.chunk_off, &g->ws.zpart,
-                      &g->ws.misc,    &g->ws.io,     &g->ws.acc,       &g->ws.meta};
+                      &g->ws.misc,    &g->ws.io,     &g->ws.acc,       &g->ws.meta,
+                      &g->ws.feat};
     for (DevBuf *b : bufs) b->release();
     for (ProfRec &r : g->prof.recs) {
         (void)hipEventDestroy(r.a);
@@ -299,7 +314,7 @@ geer_status geer_profile_read(geer_graph *g, geer_kernel_profile *out, int32_t c
     GEER_TRY(prof_flush(g));
     static const char *names[PK_COUNT] = {"hop_light", "hop_segments", "hop_heavy_fin", "hop1",
                                           "colstat", "epilogue", "walk", "amc_plan", "amc_stop",
-                                          "features", "mlp", "hop2_global", "hop2_lds"};
+                                          "features", "mlp", "hop2_global", "hop2_lds", "dense_hop"};
     int32_t k = 0;
     for (int i = 0; i < PK_COUNT && k < cap; ++i) {
         geer_kernel_profile &r = out[k++];

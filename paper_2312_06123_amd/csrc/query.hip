@@ -133,7 +133,8 @@ struct SlotMeta {
 
 // Host view of one group: which batch sits in which slot and its queries.
 struct GroupPlan {
-    int64_t b0 = 0, nbat = 0;  // first batch and batch count
+    int64_t p0 = 0, nbat = 0;  // first position and batch count
+    int64_t pend = 0;          // end of the phase (positions)
     int B = 64;
 };
 
@@ -163,6 +164,7 @@ static geer_status launch_level(geer_graph *g, const QueryCtx &c, const SlotView
             }
         }
         sparse = work <= 2.0 * (double)g->nnz;
+        if (sparse) prof_add_units(g, PK_HOP2_LDS, work);
     }
     if (sparse) {
         if (ws.a_dirty[k]) {
@@ -235,8 +237,8 @@ static geer_status smm_group(geer_graph *g, const QueryCtx &c, const SlotView &s
     std::vector<int> nbs(G);
     int levels = 0;
     for (int k = 0; k < G; ++k) {
-        q0s[k] = (gp.b0 + k) * gp.B;
-        nbs[k] = (int)std::min<int64_t>(gp.B, c.nq - q0s[k]);
+        q0s[k] = gp.p0 + (int64_t)k * gp.B;
+        nbs[k] = (int)std::min<int64_t>(gp.B, gp.pend - q0s[k]);
         recs[k] = BatchRec();
         recs[k].q0 = q0s[k];
         recs[k].nb = nbs[k];
@@ -306,6 +308,7 @@ static geer_status smm_group(geer_graph *g, const QueryCtx &c, const SlotView &s
 
 static int default_col_tile(const geer_graph *g, int vs)
 {
+    if (g->tuned_col_tile && vs == 4) return g->tuned_col_tile;
     // keep one column tile of the vectors within the 256 MB last-level cache
     const double tile_bytes_128 = (double)g->n * kCols * vs;
     if (tile_bytes_128 <= 96e6) return 128;
@@ -353,42 +356,59 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
     GEER_TRY(ensure_slots(g, G, vs));
     GEER_TRY(g->ws.meta.reserve((6 * (size_t)G + (size_t)G * (max_hops + 2)) * 8 + 64));
     GEER_TRY(launch_init_queries(g, c, d_fixed, -1, c.stream));
-    const bool is_static = p.schedule != GEER_SCHEDULE_GREEDY;
-    std::vector<int32_t> ord(c.nq), target;
+    const bool learned = p.schedule == GEER_SCHEDULE_LEARNED;
+    if (learned) c.tau = std::max(c.tau, kLearnedTauMax);
+    std::vector<int32_t> ord(c.nq), target(c.nq, 0);
     for (int64_t i = 0; i < c.nq; ++i) ord[i] = (int32_t)i;
-    if (is_static) {
+    int64_t n_static = 0;  // positions [0, n_static) run a static plan, the rest greedy
+    if (p.schedule != GEER_SCHEDULE_GREEDY) {
+        if (learned) {
+            GEER_TRY(g->ws.feat.reserve((size_t)c.nq * GEER_MLP_FEATURES * sizeof(float)));
+            GEER_TRY(launch_learned(g, c, p.model, g->ws.feat.as<float>(), c.tau, c.stream));
+        }
         // depths are known: bucket pairs of equal SMM depth into the same
         // batches so that dense hops run on full batches
-        target.resize(c.nq);
+        std::vector<int32_t> ellh(c.nq), act(c.nq), fb(c.nq);
         GEER_HIP(hipMemcpyAsync(target.data(), c.qs.lb_target, c.nq * sizeof(int32_t),
                                 hipMemcpyDeviceToHost, c.stream));
-        std::vector<int32_t> ellh(c.nq), act(c.nq);
         GEER_HIP(hipMemcpyAsync(ellh.data(), c.qs.ell, c.nq * sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
         GEER_HIP(hipMemcpyAsync(act.data(), c.qs.active_smm, c.nq * sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+        GEER_HIP(hipMemcpyAsync(fb.data(), c.qs.fallback, c.nq * sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
         GEER_HIP(hipStreamSynchronize(c.stream));
         for (int64_t i = 0; i < c.nq; ++i) target[i] = act[i] ? std::min(target[i], ellh[i]) : 0;
-        std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return target[a] > target[b]; });
+        std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+            if (fb[a] != fb[b]) return fb[a] < fb[b];  // fallback pairs last
+            return target[a] > target[b];
+        });
+        n_static = 0;
+        while (n_static < c.nq && !fb[ord[n_static]]) ++n_static;
     }
     GEER_HIP(hipMemcpyAsync(c.qs.ord, ord.data(), c.nq * sizeof(int32_t), hipMemcpyHostToDevice, c.stream));
     SlotView sv{g->ws.pool.as<char>(), g->ws.bits.as<uint32_t>(), (size_t)g->n, vs};
     SlotMeta sm{g->ws.meta.as<uint64_t>(), G};
     std::vector<BatchRec> recs(G);
-    for (int64_t b0 = 0; b0 < nbatches; b0 += G) {
-        GroupPlan gp;
-        gp.b0 = b0;
-        gp.nbat = std::min<int64_t>(nbatches, b0 + G) - b0;
-        gp.B = B;
-        sm.base = g->ws.meta.as<uint64_t>();
-        GEER_TRY(smm_group(g, c, sv, sm, gp, is_static, target.data(), h_s, h_t, ord.data(), col_tile,
-                           max_hops, recs));
-        sm.base = g->ws.meta.as<uint64_t>();
-        AmcGroup grp;
-        grp.q0 = b0 * B;
-        grp.nq = std::min<int64_t>(c.nq, (b0 + gp.nbat) * B) - grp.q0;
-        grp.pool = sv.pool;
-        grp.value_size = vs;
-        GEER_TRY(amc_phase(g, c, grp, c.stream, p.walk_ilp));
-        for (int k = 0; k < gp.nbat; ++k) GEER_TRY(cleanup_batch(g, c, sv, sm, k, recs[k]));
+    for (int phase = 0; phase < 2; ++phase) {
+        const bool is_static = phase == 0;
+        const int64_t pb = is_static ? 0 : n_static, pe = is_static ? n_static : c.nq;
+        const int64_t nbat_phase = (pe - pb + B - 1) / B;
+        for (int64_t b0 = 0; b0 < nbat_phase; b0 += G) {
+            GroupPlan gp;
+            gp.p0 = pb + b0 * B;
+            gp.nbat = std::min<int64_t>(nbat_phase, b0 + G) - b0;
+            gp.pend = pe;
+            gp.B = B;
+            sm.base = g->ws.meta.as<uint64_t>();
+            GEER_TRY(smm_group(g, c, sv, sm, gp, is_static, target.data(), h_s, h_t, ord.data(),
+                               col_tile, max_hops, recs));
+            sm.base = g->ws.meta.as<uint64_t>();
+            AmcGroup grp;
+            grp.q0 = gp.p0;
+            grp.nq = std::min<int64_t>(pe, gp.p0 + gp.nbat * B) - grp.q0;
+            grp.pool = sv.pool;
+            grp.value_size = vs;
+            GEER_TRY(amc_phase(g, c, grp, c.stream, p.walk_ilp));
+            for (int k = 0; k < gp.nbat; ++k) GEER_TRY(cleanup_batch(g, c, sv, sm, k, recs[k]));
+        }
     }
     return GEER_OK;
 }
@@ -434,8 +454,6 @@ geer_status geer_query(geer_graph *g, int64_t nq, const int32_t *s, const int32_
         if (!(eps[i] > 0.0) || std::isinf(eps[i]))
             return fail(GEER_E_INVALID_ARG, "query " + std::to_string(i) + ": eps must be > 0 and finite");
     }
-    if (p.schedule == GEER_SCHEDULE_LEARNED)
-        return fail(GEER_E_MODEL, "learned scheduling is not available in this build");
     if (nq == 0) return GEER_OK;
     GEER_HIP(hipSetDevice(g->device));
     hipStream_t st = pick_stream(g, p);
@@ -486,8 +504,6 @@ geer_status geer_query_device(geer_graph *g, int64_t nq, const int32_t *d_s, con
     if (!g->has_lambda) return fail(GEER_E_NO_LAMBDA, "lambda has not been set");
     if (p.schedule == GEER_SCHEDULE_FIXED && nq > 0 && !p.fixed_ell_b)
         return fail(GEER_E_INVALID_ARG, "FIXED schedule needs fixed_ell_b");
-    if (p.schedule == GEER_SCHEDULE_LEARNED)
-        return fail(GEER_E_MODEL, "learned scheduling is not available in this build");
     if (nq == 0) return GEER_OK;
     GEER_HIP(hipSetDevice(g->device));
     hipStream_t st = pick_stream(g, p);
@@ -586,8 +602,9 @@ geer_status geer_smm(geer_graph *g, int32_t nq, const int32_t *s, const int32_t 
     std::vector<BatchRec> recs(1);
     if (hops > 0) {
         GroupPlan gp;
-        gp.b0 = 0;
+        gp.p0 = 0;
         gp.nbat = 1;
+        gp.pend = nq;
         gp.B = nq;
         GEER_TRY(smm_group(g, c, sv, sm, gp, true, target.data(), s, t, ord.data(), tile, hops, recs));
     }

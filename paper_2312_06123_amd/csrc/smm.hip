@@ -619,6 +619,7 @@ geer_status launch_hop_dense(geer_graph *g, const HopArgs &a, int value_size, hi
     GEER_TRY(ws.segbuf.reserve((size_t)std::max(g->n_seg, 1) *
                                (kCols * (size_t)value_size + kBitWords * sizeof(uint32_t))));
     const int kt = a.col_tile;
+    const int whole = prof_begin(g, st);
     for (int c0 = 0; c0 < kCols; c0 += kt) {
         // a tile without an active pair has nothing to compute (its columns
         // are not read again: stopped pairs keep their vectors elsewhere)
@@ -649,6 +650,7 @@ geer_status launch_hop_dense(geer_graph *g, const HopArgs &a, int value_size, hi
                        (int)prows, a.mask, cs_m1, cs_m2, cs_sd);
     prof_end(g, tok, PK_COLSTAT, 0.0, 0.0, st);
     GEER_HIP(hipGetLastError());
+    prof_end(g, whole, PK_DENSE_HOP, 0.0, 1.0, st);
     return GEER_OK;
 }
 
@@ -703,12 +705,13 @@ __global__ void k_epilogue(QState qs, int64_t q0, int nb, int hop, const T *__re
     const int32_t ell = qs.ell[q];
     const int32_t lf = ell - hop;
     const double eps = qs.eps[q];
+    tau = qs.tau_q[q];  // per-pair batch count (the learned schedule may set it)
     const double psi = psi_of(lf, cs_m1[cs], cs_m2[cs], cs_m1[ct], cs_m2[ct], ids, idt);
     const double es = eta_star_of(psi, eps, tau, delta);
     const int64_t e1 = eta1_of(es, tau);
     const int64_t sd = cs_sd[cs] + cs_sd[ct];
     bool stop = hop >= qs.lb_target[q];
-    if (!stop && schedule == GEER_SCHEDULE_GREEDY) {
+    if (!stop && (schedule == GEER_SCHEDULE_GREEDY || qs.fallback[q])) {
         // Eq. (smm-amc): next-hop cost sum_{V_s} d + sum_{V_t} d versus h(l - l_b)
         const double h = (ldexp(1.0, tau) - 1.0) * (double)e1;
         stop = (double)sd > h;

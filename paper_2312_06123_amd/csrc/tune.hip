@@ -1,0 +1,120 @@
+// Autotuner: SpMM column tile and the per-unit costs of the GEER phases on
+// the current device and graph, with an optional on-disk cache.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "geer_internal.h"
+
+using namespace geer;
+
+static std::string tune_key(const geer_graph *g)
+{
+    hipDeviceProp_t prop;
+    std::string dev = "unknown";
+    if (hipGetDeviceProperties(&prop, g->device) == hipSuccess) dev = prop.gcnArchName;
+    for (char &ch : dev)
+        if (ch == ' ' || ch == '\t') ch = '_';
+    return std::to_string(g->n) + " " + std::to_string(g->nnz) + " " + std::to_string(g->max_deg) +
+           " " + dev;
+}
+
+static bool cache_lookup(const char *path, const std::string &key, geer_tuning *t)
+{
+    if (!path) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        long long n, nnz, md;
+        char dev[128];
+        int tile;
+        double a, b, c;
+        if (std::sscanf(line, "%lld %lld %lld %127s %d %lf %lf %lf", &n, &nnz, &md, dev, &tile, &a, &b,
+                        &c) != 8)
+            continue;
+        std::string k = std::to_string(n) + " " + std::to_string(nnz) + " " + std::to_string(md) + " " + dev;
+        if (k == key && (tile == 32 || tile == 64 || tile == 128) && a > 0 && b > 0 && c > 0) {
+            t->col_tile = tile;
+            t->ns_per_walk_step = a;
+            t->ns_per_hop2_unit = b;
+            t->ns_per_dense_hop = c;
+            found = true;  // the last matching entry wins
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+extern "C" geer_status geer_autotune(geer_graph *g, int64_t nq, const int32_t *s, const int32_t *t,
+                                     const double *eps, const char *cache_path, geer_tuning *out)
+{
+    if (!g || !out) return fail(GEER_E_INVALID_ARG, "NULL argument");
+    if (nq < 1 || !s || !t || !eps) return fail(GEER_E_INVALID_ARG, "need a sample of pairs");
+    if (!g->has_lambda) return fail(GEER_E_NO_LAMBDA, "lambda has not been set");
+    geer_tuning tn;
+    std::memset(&tn, 0, sizeof(tn));
+    const std::string key = tune_key(g);
+    if (cache_lookup(cache_path, key, &tn)) {
+        tn.from_cache = 1;
+    } else {
+        std::vector<double> r(nq);
+        std::vector<int32_t> three(nq, 3);
+        geer_params p;
+        geer_params_default(&p);
+        geer_kernel_profile prof[32];
+        int32_t cnt = 0;
+        // 1. dense-hop time per batch for each column tile (depth 3: one dense hop)
+        double best = 1e300;
+        const int tiles[3] = {32, 64, 128};
+        for (int kt : tiles) {
+            p.schedule = GEER_SCHEDULE_FIXED;
+            p.fixed_ell_b = three.data();
+            p.col_tile = kt;
+            GEER_TRY(geer_query(g, nq, s, t, eps, &p, r.data(), nullptr));  // warm-up
+            GEER_TRY(geer_profile_enable(g, 1));
+            GEER_TRY(geer_query(g, nq, s, t, eps, &p, r.data(), nullptr));
+            GEER_TRY(geer_profile_read(g, prof, 32, &cnt));
+            GEER_TRY(geer_profile_enable(g, 0));
+            const geer_kernel_profile &d = prof[PK_DENSE_HOP];
+            if (d.launches > 0) {
+                const double ns = 1e6 * d.total_ms / (double)d.launches;
+                if (ns < best) {
+                    best = ns;
+                    tn.col_tile = kt;
+                }
+            }
+        }
+        if (tn.col_tile == 0) tn.col_tile = 32;
+        tn.ns_per_dense_hop = best < 1e300 ? best : 1e6;
+        // 2. walk-step and hop-2 unit costs from the greedy schedule
+        p.schedule = GEER_SCHEDULE_GREEDY;
+        p.fixed_ell_b = nullptr;
+        p.col_tile = tn.col_tile;
+        GEER_TRY(geer_profile_enable(g, 1));
+        GEER_TRY(geer_query(g, nq, s, t, eps, &p, r.data(), nullptr));
+        GEER_TRY(geer_profile_read(g, prof, 32, &cnt));
+        GEER_TRY(geer_profile_enable(g, 0));
+        const geer_kernel_profile &w = prof[PK_WALK];
+        tn.ns_per_walk_step = w.work_units > 0 ? 1e6 * w.total_ms / w.work_units : 0.05;
+        const double h2_ms = prof[PK_HOP2_LDS].total_ms + prof[PK_HOP2_SPARSE].total_ms;
+        const double h2_units = prof[PK_HOP2_LDS].work_units;
+        tn.ns_per_hop2_unit = h2_units > 0 ? 1e6 * h2_ms / h2_units : 0.3;
+        if (cache_path) {
+            FILE *f = std::fopen(cache_path, "a");
+            if (f) {
+                std::fprintf(f, "%s %d %.6g %.6g %.6g\n", key.c_str(), tn.col_tile, tn.ns_per_walk_step,
+                             tn.ns_per_hop2_unit, tn.ns_per_dense_hop);
+                std::fclose(f);
+            }
+        }
+    }
+    tn.rho2 = tn.ns_per_hop2_unit / tn.ns_per_walk_step;
+    tn.rhod = tn.ns_per_dense_hop / 64.0 / tn.ns_per_walk_step;
+    g->tuned_col_tile = tn.col_tile;
+    GEER_TRY(geer_graph_set_costs(g, tn.rho2, tn.rhod));
+    *out = tn;
+    return GEER_OK;
+}

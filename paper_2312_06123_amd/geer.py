@@ -43,9 +43,15 @@ EXPORTED = [
     "geer_graph_get_lambda", "geer_graph_compute_lambda", "geer_graph_info", "geer_query",
     "geer_query_device", "geer_smm", "geer_walk_traces", "geer_amc", "geer_last_error",
     "geer_version", "geer_model_create", "geer_model_free", "geer_model_save", "geer_model_load",
-    "geer_model_get_params", "geer_model_set_params", "geer_features", "geer_mlp_forward",
-    "geer_mlp_train_step", "geer_autotune", "geer_profile_enable", "geer_profile_read",
+    "geer_model_get_params", "geer_model_set_params", "geer_model_set_norm",
+    "geer_graph_set_costs", "geer_features", "geer_mlp_forward", "geer_mlp_grad",
+    "geer_mlp_train", "geer_autotune", "geer_profile_enable", "geer_profile_read",
 ]
+
+MLP_FEATURES = 13
+MLP_HIDDEN = 64
+MLP_OUTPUTS = 3
+MLP_PARAMS = 13 * 64 + 64 + 64 * 64 + 64 + 64 * 3 + 3
 
 
 class GeerError(RuntimeError):
@@ -119,16 +125,19 @@ _SIGNATURES = {
     "geer_amc": ([_vp, _i32, _i32, _vp, _vp, _f64, _i32, _i32, _f64, _u64, _u32, _u32, _vp, _vp], _i32),
     "geer_last_error": ([], ctypes.c_char_p),
     "geer_version": ([], ctypes.c_char_p),
-    "geer_model_create": ([_i32, _i32, _u64, ctypes.POINTER(_vp)], _i32),
+    "geer_model_create": ([_u64, ctypes.POINTER(_vp)], _i32),
     "geer_model_free": ([_vp], None),
     "geer_model_save": ([_vp, ctypes.c_char_p], _i32),
     "geer_model_load": ([ctypes.c_char_p, ctypes.POINTER(_vp)], _i32),
     "geer_model_get_params": ([_vp, _vp, _i64], _i32),
     "geer_model_set_params": ([_vp, _vp, _i64], _i32),
-    "geer_features": ([_vp, _i64, _vp, _vp, _vp, _vp, _vp], _i32),
+    "geer_model_set_norm": ([_vp, _vp, _vp, _vp, _vp], _i32),
+    "geer_graph_set_costs": ([_vp, _f64, _f64], _i32),
+    "geer_features": ([_vp, _i64, _vp, _vp, _vp, _vp], _i32),
     "geer_mlp_forward": ([_vp, _i64, _vp, _i32, _vp], _i32),
-    "geer_mlp_train_step": ([_vp, _i64, _vp, _vp, _vp, _f64, _vp, _vp], _i32),
-    "geer_autotune": ([_vp, _vp, _vp], _i32),
+    "geer_mlp_grad": ([_vp, _i32, _vp, _vp, _vp, _vp], _i32),
+    "geer_mlp_train": ([_vp, _i64, _vp, _vp, _vp, _i32, _i32, _f64, _vp, _vp], _i32),
+    "geer_autotune": ([_vp, _i64, _vp, _vp, _vp, ctypes.c_char_p, _vp], _i32),
     "geer_profile_enable": ([_vp, _i32], _i32),
     "geer_profile_read": ([_vp, _vp, _i32, ctypes.POINTER(_i32)], _i32),
 }
@@ -317,6 +326,95 @@ def geer_profile_read(g) -> dict:
     return {r.name.decode(): {"launches": r.launches, "total_ms": r.total_ms,
                               "alg_bytes": r.alg_bytes, "work_units": r.work_units}
             for r in recs[:cnt.value]}
+
+
+class geer_tuning(ctypes.Structure):
+    _fields_ = [("col_tile", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("ns_per_walk_step", ctypes.c_double), ("ns_per_hop2_unit", ctypes.c_double),
+                ("ns_per_dense_hop", ctypes.c_double), ("rho2", ctypes.c_double),
+                ("rhod", ctypes.c_double)]
+
+
+def geer_autotune(g, s, t, eps, cache_path: str | None = None) -> dict:
+    s = np.ascontiguousarray(s, dtype=np.int32)
+    t = np.ascontiguousarray(t, dtype=np.int32)
+    e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, dtype=np.float64), s.shape))
+    out = geer_tuning()
+    _check(_lib.geer_autotune(g, s.size, _ptr(s), _ptr(t), _ptr(e),
+                              cache_path.encode() if cache_path else None, ctypes.byref(out)))
+    return {k: getattr(out, k) for k, _ in geer_tuning._fields_}
+
+
+def geer_graph_set_costs(g, rho2: float, rhod: float) -> None:
+    _check(_lib.geer_graph_set_costs(g, float(rho2), float(rhod)))
+
+
+def geer_features(g, s, t, eps) -> np.ndarray:
+    s = np.ascontiguousarray(s, dtype=np.int32)
+    t = np.ascontiguousarray(t, dtype=np.int32)
+    e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, dtype=np.float64), s.shape))
+    out = np.zeros((s.size, MLP_FEATURES), dtype=np.float32)
+    _check(_lib.geer_features(g, s.size, _ptr(s), _ptr(t), _ptr(e), _ptr(out)))
+    return out
+
+
+class Model:
+    """Owning wrapper of a geer_model handle (the learned scheduler)."""
+
+    def __init__(self, seed: int = 0, path: str | None = None):
+        self.handle = ctypes.c_void_p()
+        if path is not None:
+            _check(_lib.geer_model_load(path.encode(), ctypes.byref(self.handle)))
+        else:
+            _check(_lib.geer_model_create(int(seed), ctypes.byref(self.handle)))
+
+    def close(self):
+        if self.handle:
+            _lib.geer_model_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def save(self, path: str) -> None:
+        _check(_lib.geer_model_save(self.handle, path.encode()))
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(MLP_PARAMS, dtype=np.float32)
+        _check(_lib.geer_model_get_params(self.handle, _ptr(out), MLP_PARAMS))
+        return out
+
+    def set_params(self, p) -> None:
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        _check(_lib.geer_model_set_params(self.handle, _ptr(p), p.size))
+
+    def set_norm(self, mean, std, lo, hi) -> None:
+        arr = [np.ascontiguousarray(a, dtype=np.float32) for a in (mean, std, lo, hi)]
+        _check(_lib.geer_model_set_norm(self.handle, *[_ptr(a) for a in arr]))
+
+    def forward(self, x, bf16: bool = False) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.zeros((x.shape[0], MLP_OUTPUTS), dtype=np.float32)
+        _check(_lib.geer_mlp_forward(self.handle, x.shape[0], _ptr(x), 1 if bf16 else 0, _ptr(y)))
+        return y
+
+    def grad(self, x, y, w) -> np.ndarray:
+        x, y, w = [np.ascontiguousarray(a, dtype=np.float32) for a in (x, y, w)]
+        g = np.zeros(MLP_PARAMS, dtype=np.float32)
+        _check(_lib.geer_mlp_grad(self.handle, x.shape[0], _ptr(x), _ptr(y), _ptr(w), _ptr(g)))
+        return g
+
+    def train(self, x, y, w, steps: int, batch: int = 64, lr: float = 1e-3, order=None):
+        x, y, w = [np.ascontiguousarray(a, dtype=np.float32) for a in (x, y, w)]
+        loss = np.zeros(max(steps, 1), dtype=np.float32)
+        o = None if order is None else np.ascontiguousarray(order, dtype=np.int64)
+        _check(_lib.geer_mlp_train(self.handle, x.shape[0], _ptr(x), _ptr(y), _ptr(w), int(steps),
+                                   int(batch), float(lr), _ptr(o) if o is not None else None,
+                                   _ptr(loss)))
+        return loss[:steps]
 
 
 class Graph:

@@ -1,0 +1,165 @@
+"""Training pipeline of the learned SMM/AMC scheduler.
+
+The network (13 features -> 64 -> 64 -> 3) predicts, per pair, the SMM depth
+l_b and the AMC batch count tau that minimise the pair's cost on the GPU, and
+log10 of the resulting absolute error.  Training data comes from GEER runs of
+this library itself:
+
+  * every training pair is answered with each fixed schedule (l_b, tau) of a
+    small grid (FIXED schedule, per-pair depth clamped to l);
+  * a pair's cost under a schedule, in units of one walk step, is
+        steps + rho2 * W2 * [l_b >= 2] + rhod * max(l_b - 2, 0)
+    where steps = 2 * walk pairs * (l - l_b) is the AMC work, W2 the sparse
+    hop-2 work (neighbour-degree sums of s and t) and rhod the cost of one
+    dense hop per pair of a full batch; rho2 and rhod vary between devices and
+    graphs, so each pair is labelled under several sampled (rho2, rhod) and
+    the two ratios are inputs of the network (the autotuner measures them on
+    the graph the model is used on);
+  * the label is the cheapest schedule; its error is measured against the
+    library's own SMM-only answer at a tight eps (Theorem 3.1 bounds that
+    reference's truncation error by eps_ref / 2).
+
+Training runs on the GPU through the library's own forward/backward/Adam
+kernels (geer_mlp_train).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import geer as G
+from . import inputs as I
+
+DEPTHS = (1, 2, 3, 4)
+TAUS = (2, 3, 5, 8)
+EPS_REF = 1e-3
+
+
+def log(msg):
+    print(f"[scheduler] {msg}", file=sys.stderr, flush=True)
+
+
+def sweep(gg, s, t, eps, seed=7):
+    """Run every fixed (l_b, tau) on the pairs -> dict (lb, tau) -> stats."""
+    out = {}
+    for lb in DEPTHS:
+        for tau in TAUS:
+            p = G.geer_params_default(seed=seed, tau=tau)
+            r, st = G.geer_query(gg.handle, s, t, eps, p, stats=True, fixed_ell_b=lb)
+            out[(lb, tau)] = (r, st)
+    return out
+
+
+def reference(gg, s, t):
+    """SMM-only answers at eps_ref (|r_ref - r| <= eps_ref / 2, Theorem 3.1)."""
+    p = G.geer_params_default(flags=G.GEER_FLAG_FP64_VECTORS)
+    return G.geer_query(gg.handle, s, t, EPS_REF, p, fixed_ell_b=1 << 20)
+
+
+def label(feats, runs, r_ref, rng, n_rho=4):
+    """Labelled samples (X raw, Y, W) with sampled cost ratios."""
+    n = feats.shape[0]
+    keys = list(runs)
+    w2 = (2.0 ** feats[:, 3] - 1.0) + (2.0 ** feats[:, 4] - 1.0)
+    cost_parts = []
+    for (lb, tau) in keys:
+        _, st = runs[(lb, tau)]
+        steps = 2.0 * st["walk_pairs"] * np.maximum(st["ell"] - st["ell_b"], 0)
+        eff = st["ell_b"]
+        cost_parts.append((steps, eff))
+    Xs, Ys, Ws = [], [], []
+    for _ in range(n_rho):
+        rho2 = 2.0 ** rng.uniform(-1.0, 6.0, n)
+        rhod = 2.0 ** rng.uniform(10.0, 27.0, n)
+        costs = np.stack([steps + rho2 * w2 * (eff >= 2) + rhod * np.maximum(eff - 2, 0)
+                          for steps, eff in cost_parts], axis=1)
+        best = np.argmin(costs, axis=1)
+        y = np.zeros((n, 3), dtype=np.float32)
+        for i in range(n):
+            lb, tau = keys[best[i]]
+            r, st = runs[(lb, tau)]
+            y[i, 0] = st["ell_b"][i]
+            y[i, 1] = tau
+            y[i, 2] = np.log10(abs(r[i] - r_ref[i]) + 1e-6)
+        x = feats.copy()
+        x[:, 11] = np.log2(rho2)
+        x[:, 12] = np.log2(rhod)
+        Xs.append(x)
+        Ys.append(y)
+        Ws.append(np.tile(np.array([[1.0, 0.25, 0.5]], dtype=np.float32), (n, 1)))
+    return np.concatenate(Xs), np.concatenate(Ys), np.concatenate(Ws)
+
+
+def graph_runs(g, nq, eps, seed, rng):
+    """Features, schedule sweep and reference answers on one training graph."""
+    s, t = I.uniform_pairs(g.n, nq, seed)
+    with G.Graph(g.n, g.row_ptr32(), g.col_idx) as gg:
+        lam = G.geer_graph_compute_lambda(gg.handle, 300, 1e-9, seed)
+        t0 = time.time()
+        runs = sweep(gg, s, t, eps, seed)
+        log(f"{g.name}: {len(runs) * nq} GEER runs in {time.time() - t0:.1f} s (lambda={lam:.4f})")
+        r_ref = reference(gg, s, t)
+        feats = G.geer_features(gg.handle, s, t, eps)
+    return label(feats, runs, r_ref, rng)
+
+
+def train_model(X, Y, W, steps=30000, seed=11, lr=2e-3):
+    m = G.Model(seed=seed)
+    mean = X.mean(axis=0)
+    std = X.std(axis=0) + 1e-3
+    m.set_norm(mean, std, X.min(axis=0), X.max(axis=0))
+    Z = (X - mean) / std
+    losses = []
+    for phase, (n, rate) in enumerate(((steps // 2, lr), (steps // 4, lr / 4), (steps // 4, lr / 16))):
+        losses.append(m.train(Z, Y, W, n, 64, rate))
+    return m, np.concatenate(losses), (mean, std)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--er-queries", type=int, default=6000)
+    ap.add_argument("--cl-queries", type=int, default=6500)
+    ap.add_argument("--cl-nodes", type=int, default=200_000)
+    ap.add_argument("--eps", type=float, default=0.05)
+    ap.add_argument("--steps", type=int, default=30000)
+    ap.add_argument("--report", default=None)
+    a = ap.parse_args(argv)
+    rng = np.random.default_rng(4)
+    parts = []
+    # the small uniform-random graph of the correctness configuration
+    g1 = I.erdos_renyi_path(10_000, 10, 1001)
+    parts.append(graph_runs(g1, a.er_queries, a.eps, 4001, rng))
+    # a small power-law graph: the uniform graph has no degree skew, so its
+    # features cannot cover the hub-dominated graphs the model is used on
+    if a.cl_queries > 0:
+        g2 = I.chung_lu(a.cl_nodes, 2.1, 20, 5004)
+        parts.append(graph_runs(g2, a.cl_queries, a.eps, 4002, rng))
+    X = np.concatenate([p[0] for p in parts])
+    Y = np.concatenate([p[1] for p in parts])
+    W = np.concatenate([p[2] for p in parts])
+    runs_total = (a.er_queries + a.cl_queries) * len(DEPTHS) * len(TAUS)
+    log(f"{X.shape[0]} labelled samples from {runs_total} GEER runs")
+    t0 = time.time()
+    m, losses, _ = train_model(X, Y, W, a.steps)
+    log(f"trained {a.steps} steps in {time.time() - t0:.1f} s; loss {losses[:200].mean():.4f} -> "
+        f"{losses[-200:].mean():.4f}")
+    m.save(a.out)
+    if a.report:
+        with open(a.report, "w") as f:
+            json.dump({"samples": int(X.shape[0]), "runs": runs_total,
+                       "loss_first": float(losses[:200].mean()),
+                       "loss_last": float(losses[-200:].mean()),
+                       "label_lb_hist": np.bincount(Y[:, 0].astype(int)).tolist(),
+                       "label_tau_hist": np.bincount(Y[:, 1].astype(int)).tolist()}, f)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -408,3 +408,51 @@ def test_geer_same_node_and_stats():
     r, st = oracle.geer(g.row_ptr, g.col_idx, [2, 1], [2, 4], 0.1, 0.2)
     assert r[0] == 0.0 and st[0]["ell"] == 0
     assert abs(r[1] - 2 / 6) <= 0.1
+
+
+# ---------------------------------------------------------------------------
+# learned-scheduler network reference
+# ---------------------------------------------------------------------------
+
+def test_mlp_reference_gradient_matches_finite_differences():
+    from oracle import mlp
+
+    rng = np.random.default_rng(0)
+    p = rng.normal(0, 0.3, mlp.P)
+    X = rng.normal(0, 1, (9, mlp.F))
+    Y = rng.normal(0, 1, (9, mlp.O))
+    Wt = rng.random((9, mlp.O))
+    g = mlp.grad(p, X, Y, Wt)
+    h = 1e-6
+    for k in rng.choice(mlp.P, 60, replace=False):
+        e = np.zeros(mlp.P)
+        e[k] = h
+        fd = (mlp.loss(p + e, X, Y, Wt) - mlp.loss(p - e, X, Y, Wt)) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_mlp_reference_adam_reduces_loss():
+    from oracle import mlp
+
+    rng = np.random.default_rng(1)
+    X = rng.normal(0, 1, (64, mlp.F))
+    Y = np.stack([X[:, 0] + 2 * X[:, 1], X[:, 2] ** 2, np.sin(X[:, 3])], axis=1)
+    Wt = np.ones_like(Y)
+    p = rng.normal(0, 0.2, mlp.P)
+    m = np.zeros(mlp.P)
+    v = np.zeros(mlp.P)
+    l0 = mlp.loss(p, X, Y, Wt)
+    for step in range(1, 301):
+        p, m, v = mlp.adam_step(p, m, v, mlp.grad(p, X, Y, Wt), step, 3e-3)
+    assert mlp.loss(p, X, Y, Wt) < 0.2 * l0
+
+
+def test_geer_per_pair_tau_matches_uniform_tau():
+    g = I.erdos_renyi_path(300, 6, 44)
+    lam = oracle.lambda_dense(g.row_ptr, g.col_idx)
+    s, t = I.uniform_pairs(g.n, 40, 45)
+    for tau in (1, 3, 5):
+        r1, st1 = oracle.geer(g.row_ptr, g.col_idx, s, t, 0.2, lam, tau=tau, seed=2)
+        r2, st2 = oracle.geer(g.row_ptr, g.col_idx, s, t, 0.2, lam, tau=5, seed=2,
+                              tau_per_pair=np.full(len(s), tau))
+        assert np.array_equal(r1, r2) and np.array_equal(st1["batches_run"], st2["batches_run"])
