@@ -109,6 +109,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--col-tile", type=int, default=0)
     ap.add_argument("--group-batches", type=int, default=0)
+    ap.add_argument("--model", default=os.path.join(ROOT, "paper_2312_06123_amd", "data",
+                                                    "scheduler.geermlp"))
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the query set shards across GPUs with no "
@@ -136,17 +138,38 @@ def main() -> int:
     dr = torch.zeros(len(s), dtype=torch.float64, device="cuda")
     seed = 3002
 
+    # autotune on a separate sample of pairs (column tile, unit costs -> cost features)
+    ts, tt = I.uniform_pairs(g.n, 1024, 2102)
+    t0 = time.perf_counter()
+    tune = G.geer_autotune(gg.handle, ts, tt, args.eps)
+    log(f"autotune: col_tile={tune['col_tile']} ns/step={tune['ns_per_walk_step']:.4f} "
+        f"ns/hop2-unit={tune['ns_per_hop2_unit']:.4f} ns/dense-hop={tune['ns_per_dense_hop']:.0f} "
+        f"({time.perf_counter() - t0:.1f} s)")
+    model = G.Model(path=args.model)
+
     def plain_params():
         return G.geer_params_default(seed=seed, col_tile=args.col_tile,
                                      group_batches=args.group_batches)
+
+    def learned_params():
+        return G.geer_params_default(seed=seed, col_tile=args.col_tile,
+                                     group_batches=args.group_batches,
+                                     schedule=G.GEER_SCHEDULE_LEARNED, model=model.handle.value)
 
     log("plain GEER (greedy switch rule)")
     plain = run_schedule(G, gg, ds, dt, de, dr, len(s), args.steps, args.warmup, plain_params,
                          torch)
     r_plain = dr.cpu().numpy()
     log(f"plain: {plain['value']:.1f} pairs/s, {plain['ms_per_step']:.1f} ms/step")
-    head = plain
-    head_name = "plain GEER (greedy schedule)"
+    log("batched + learned schedule")
+    learned = run_schedule(G, gg, ds, dt, de, dr, len(s), args.steps, args.warmup, learned_params,
+                           torch)
+    r_learned = dr.cpu().numpy()
+    log(f"learned: {learned['value']:.1f} pairs/s, {learned['ms_per_step']:.1f} ms/step")
+    _, st_l = G.geer_query(gg.handle, s, t, args.eps, learned_params(), stats=True)
+    _, st_p = G.geer_query(gg.handle, s, t, args.eps, plain_params(), stats=True)
+    head = learned
+    head_name = "batched + learned schedule (greedy fallback)"
     roof, table = roofline_of(head["profile"], args.steps)
     out = {
         "metric": METRIC,
@@ -170,14 +193,23 @@ def main() -> int:
         },
         "roofline": roof,
         "plain_geer": {"value": round(plain["value"], 2),
-                       "ms_per_step": round(plain["ms_per_step"], 3)},
+                       "ms_per_step": round(plain["ms_per_step"], 3),
+                       "mean_ell_b": round(float(st_p["ell_b"].mean()), 3),
+                       "walk_steps": int((2 * st_p["walk_pairs"] * (st_p["ell"] - st_p["ell_b"])).sum())},
+        "learned": {"speedup_vs_plain": round(learned["value"] / plain["value"], 3),
+                    "fallback_frac": round(float(st_l["fallback"].mean()), 4),
+                    "mean_ell_b": round(float(st_l["ell_b"].mean()), 3),
+                    "tau_hist": np.bincount(st_l["tau"], minlength=9).tolist(),
+                    "walk_steps": int((2 * st_l["walk_pairs"] * (st_l["ell"] - st_l["ell_b"])).sum()),
+                    "max_abs_diff_vs_plain": round(float(np.max(np.abs(r_learned - r_plain))), 5)},
+        "autotune": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in tune.items()},
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                         for kk, vv in v.items()} for k, v in table.items()},
     }
     if not args.no_cpu_baseline:
         log("CPU checker baseline")
         out["cpu_baseline"] = cpu_baseline(g, s, t, args.eps, lam, seed, args.cpu_seconds)
-    out["finite_results"] = bool(np.all(np.isfinite(r_plain)))
+    out["finite_results"] = bool(np.all(np.isfinite(r_plain)) and np.all(np.isfinite(r_learned)))
     gg.close()
     print(json.dumps(out), flush=True)
     return 0

@@ -158,6 +158,7 @@ struct geer_graph {
     int32_t *d_min_nbr_deg = nullptr;      // per node: smallest neighbour degree
     double rho2 = 6.0, rhod = 1e6;         // cost ratios (learned-scheduler features)
     int tuned_col_tile = 0;                // autotuner's SpMM column tile (0: not tuned)
+    double tile_ns[3] = {0, 0, 0};         // measured time of one tile launch at 32/64/128 columns
     std::vector<int64_t> h_nbr_work;       // sum of neighbour degrees (= sparse hop-2 work)
     geer::Workspace ws;
     geer::Profiler prof;

@@ -362,12 +362,15 @@ __global__ void k_learned_apply(QState qs, int64_t nq, const float *__restrict__
     bool out_of_range = false;
     for (int f = 0; f < kF; ++f) {
         const float raw = feat[q * kF + f];
-        // range seen in training, widened by a quarter of its span
-        const float lo = norm[2 * kF + f], hi = norm[3 * kF + f];
-        const float pad = 0.25f * (hi - lo);
-        if (raw < lo - pad || raw > hi + pad) out_of_range = true;
         x[f] = (raw - norm[f]) / norm[kF + f];
-        if (fabsf(x[f]) > zmax) out_of_range = true;
+        // per-pair structural features (0..8) must lie in the range seen in
+        // training, widened by half its span; graph-level ones (lambda, eps,
+        // cost ratios) are left to the error head
+        if (f <= 8) {
+            const float lo = norm[2 * kF + f], hi = norm[3 * kF + f];
+            const float pad = 0.5f * (hi - lo);
+            if (raw < lo - pad || raw > hi + pad || fabsf(x[f]) > zmax) out_of_range = true;
+        }
     }
     mlp_eval<true>(nullptr, pb, x, o);
     const int32_t ell = qs.ell[q];

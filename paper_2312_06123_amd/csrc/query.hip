@@ -138,6 +138,32 @@ struct GroupPlan {
     int B = 64;
 };
 
+// Column tile of one dense hop.  An explicit request wins; with measured
+// tile times the cheapest is taken for this hop's active pairs (only tiles
+// holding an active pair are launched); otherwise the default.
+static int pick_tile(const geer_graph *g, int requested, uint64_t hmask, int vs)
+{
+    if (requested < 0) return -requested;  // forced by the caller
+    if (vs != 4 || g->tile_ns[0] <= 0.0) return requested;
+    const int kts[3] = {32, 64, 128};
+    double best = 1e300;
+    int pick = requested;
+    for (int i = 0; i < 3; ++i) {
+        const int kt = kts[i];
+        int tiles = 0;
+        for (int c0 = 0; c0 < kCols; c0 += kt) {
+            const uint64_t tp = kt == 128 ? ~0ull : (((1ull << (kt / 2)) - 1ull) << (c0 / 2));
+            tiles += (hmask & tp) ? 1 : 0;
+        }
+        const double cost = tiles * g->tile_ns[i];
+        if (cost < best) {
+            best = cost;
+            pick = kt;
+        }
+    }
+    return pick;
+}
+
 // One hop (h >= 2) of batch k of the group.  hmask: pairs active at this hop.
 static geer_status launch_level(geer_graph *g, const QueryCtx &c, const SlotView &sv,
                                 const SlotMeta &sm, int k, int64_t q0, int nb, int hop,
@@ -200,7 +226,7 @@ static geer_status launch_level(geer_graph *g, const QueryCtx &c, const SlotView
         a.mask = d_mask;
         a.host_mask = hmask;
         a.col0 = 0;
-        a.col_tile = col_tile;
+        a.col_tile = pick_tile(g, col_tile, hmask, sv.vs);
         GEER_TRY(launch_hop_dense(g, a, sv.vs, c.stream));
         if (wout == 1) ws.a_dirty[k] = 1;
     }
@@ -352,7 +378,7 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
     const int B = p.batch_queries ? p.batch_queries : kMaxPairs;
     const int64_t nbatches = (c.nq + B - 1) / B;
     const int G = std::min(1024, p.group_batches ? p.group_batches : default_group_batches(g, vs, nbatches));
-    const int col_tile = p.col_tile ? p.col_tile : default_col_tile(g, vs);
+    const int col_tile = p.col_tile ? -p.col_tile : default_col_tile(g, vs);
     GEER_TRY(ensure_slots(g, G, vs));
     GEER_TRY(g->ws.meta.reserve((6 * (size_t)G + (size_t)G * (max_hops + 2)) * 8 + 64));
     GEER_TRY(launch_init_queries(g, c, d_fixed, -1, c.stream));
@@ -591,7 +617,7 @@ geer_status geer_smm(geer_graph *g, int32_t nq, const int32_t *s, const int32_t 
     GEER_HIP(hipMemcpyAsync(c.qs.eps, ones.data(), nq * sizeof(double), hipMemcpyHostToDevice, st));
     GEER_TRY(launch_init_queries(g, c, nullptr, hops, st));
     SlotView sv{g->ws.pool.as<char>(), g->ws.bits.as<uint32_t>(), (size_t)g->n, vs};
-    const int tile = col_tile ? col_tile : default_col_tile(g, vs);
+    const int tile = col_tile ? -col_tile : default_col_tile(g, vs);
     c.stream = st;
     std::vector<int32_t> ord(nq), target(nq, hops);
     for (int i = 0; i < nq; ++i) ord[i] = i;

@@ -20,7 +20,7 @@ static std::string tune_key(const geer_graph *g)
            " " + dev;
 }
 
-static bool cache_lookup(const char *path, const std::string &key, geer_tuning *t)
+static bool cache_lookup(const char *path, const std::string &key, geer_tuning *t, double *tile_ns)
 {
     if (!path) return false;
     FILE *f = std::fopen(path, "r");
@@ -31,9 +31,9 @@ static bool cache_lookup(const char *path, const std::string &key, geer_tuning *
         long long n, nnz, md;
         char dev[128];
         int tile;
-        double a, b, c;
-        if (std::sscanf(line, "%lld %lld %lld %127s %d %lf %lf %lf", &n, &nnz, &md, dev, &tile, &a, &b,
-                        &c) != 8)
+        double a, b, c, t32, t64, t128;
+        if (std::sscanf(line, "%lld %lld %lld %127s %d %lf %lf %lf %lf %lf %lf", &n, &nnz, &md, dev, &tile,
+                        &a, &b, &c, &t32, &t64, &t128) != 11)
             continue;
         std::string k = std::to_string(n) + " " + std::to_string(nnz) + " " + std::to_string(md) + " " + dev;
         if (k == key && (tile == 32 || tile == 64 || tile == 128) && a > 0 && b > 0 && c > 0) {
@@ -41,6 +41,9 @@ static bool cache_lookup(const char *path, const std::string &key, geer_tuning *
             t->ns_per_walk_step = a;
             t->ns_per_hop2_unit = b;
             t->ns_per_dense_hop = c;
+            tile_ns[0] = t32;
+            tile_ns[1] = t64;
+            tile_ns[2] = t128;
             found = true;  // the last matching entry wins
         }
     }
@@ -56,8 +59,9 @@ extern "C" geer_status geer_autotune(geer_graph *g, int64_t nq, const int32_t *s
     if (!g->has_lambda) return fail(GEER_E_NO_LAMBDA, "lambda has not been set");
     geer_tuning tn;
     std::memset(&tn, 0, sizeof(tn));
+    double tn_tile_ns[3] = {0, 0, 0};
     const std::string key = tune_key(g);
-    if (cache_lookup(cache_path, key, &tn)) {
+    if (cache_lookup(cache_path, key, &tn, tn_tile_ns)) {
         tn.from_cache = 1;
     } else {
         std::vector<double> r(nq);
@@ -69,6 +73,7 @@ extern "C" geer_status geer_autotune(geer_graph *g, int64_t nq, const int32_t *s
         // 1. dense-hop time per batch for each column tile (depth 3: one dense hop)
         double best = 1e300;
         const int tiles[3] = {32, 64, 128};
+        double *tile_ns = tn_tile_ns;
         for (int kt : tiles) {
             p.schedule = GEER_SCHEDULE_FIXED;
             p.fixed_ell_b = three.data();
@@ -81,6 +86,7 @@ extern "C" geer_status geer_autotune(geer_graph *g, int64_t nq, const int32_t *s
             const geer_kernel_profile &d = prof[PK_DENSE_HOP];
             if (d.launches > 0) {
                 const double ns = 1e6 * d.total_ms / (double)d.launches;
+                tile_ns[kt == 32 ? 0 : (kt == 64 ? 1 : 2)] = ns / (128 / kt);
                 if (ns < best) {
                     best = ns;
                     tn.col_tile = kt;
@@ -105,8 +111,9 @@ extern "C" geer_status geer_autotune(geer_graph *g, int64_t nq, const int32_t *s
         if (cache_path) {
             FILE *f = std::fopen(cache_path, "a");
             if (f) {
-                std::fprintf(f, "%s %d %.6g %.6g %.6g\n", key.c_str(), tn.col_tile, tn.ns_per_walk_step,
-                             tn.ns_per_hop2_unit, tn.ns_per_dense_hop);
+                std::fprintf(f, "%s %d %.6g %.6g %.6g %.6g %.6g %.6g\n", key.c_str(), tn.col_tile,
+                             tn.ns_per_walk_step, tn.ns_per_hop2_unit, tn.ns_per_dense_hop, tn_tile_ns[0],
+                             tn_tile_ns[1], tn_tile_ns[2]);
                 std::fclose(f);
             }
         }
@@ -114,6 +121,7 @@ extern "C" geer_status geer_autotune(geer_graph *g, int64_t nq, const int32_t *s
     tn.rho2 = tn.ns_per_hop2_unit / tn.ns_per_walk_step;
     tn.rhod = tn.ns_per_dense_hop / 64.0 / tn.ns_per_walk_step;
     g->tuned_col_tile = tn.col_tile;
+    for (int i = 0; i < 3; ++i) g->tile_ns[i] = tn_tile_ns[i];
     GEER_TRY(geer_graph_set_costs(g, tn.rho2, tn.rhod));
     *out = tn;
     return GEER_OK;
