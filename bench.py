@@ -67,10 +67,38 @@ def roofline_of(prof: dict, steps: int) -> tuple[dict, dict]:
     dom = max(cands, key=lambda n: table[n]["ms_per_step"])
     ach = table[dom]["achieved_GBs"]
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
             "alg_bytes_per_launch": table[dom]["alg_bytes_per_launch"],
             "avg_launch_us": round(table[dom]["avg_launch_us"], 3)}
     return roof, table
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed PMC record, or None if the
+    kernel's source changed since the counters were taken."""
+    import hashlib
+
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[kernel]
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, KeyError, ValueError):
+        return None
+    if hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_16"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
+def spmm_roofline(prof: dict) -> dict:
+    """Dense SpMM hop (light rows + heavy segments + heavy finish) against HBM peak."""
+    ks = [k for k in ("hop_light", "hop_segments", "hop_heavy_fin") if prof.get(k, {}).get("launches")]
+    ms = sum(prof[k]["total_ms"] for k in ks)
+    by = sum(prof[k]["alg_bytes"] for k in ks)
+    if ms <= 0:
+        return {"achieved": None}
+    ach = by / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "dense_hops": prof.get("dense_hop", {}).get("launches"),
+            "ms_total": round(ms, 3)}
 
 
 def cpu_baseline(g, s, t, eps, lam, seed, budget_s):
@@ -111,6 +139,12 @@ def main() -> int:
     ap.add_argument("--group-batches", type=int, default=0)
     ap.add_argument("--model", default=os.path.join(ROOT, "paper_2312_06123_amd", "data",
                                                     "scheduler.geermlp"))
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file (a cached entry launches no calibration work)")
+    ap.add_argument("--only", choices=["both", "learned", "plain"], default="both",
+                    help="time only one schedule (profiling runs)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the query set shards across GPUs with no "
@@ -141,7 +175,13 @@ def main() -> int:
     # autotune on a separate sample of pairs (column tile, unit costs -> cost features)
     ts, tt = I.uniform_pairs(g.n, 1024, 2102)
     t0 = time.perf_counter()
-    tune = G.geer_autotune(gg.handle, ts, tt, args.eps)
+    tune = G.geer_autotune(gg.handle, ts, tt, args.eps, args.tune_cache)
+    if args.copy_calibration_mib:
+        a = torch.ones(args.copy_calibration_mib << 18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     log(f"autotune: col_tile={tune['col_tile']} ns/step={tune['ns_per_walk_step']:.4f} "
         f"ns/hop2-unit={tune['ns_per_hop2_unit']:.4f} ns/dense-hop={tune['ns_per_dense_hop']:.0f} "
         f"({time.perf_counter() - t0:.1f} s)")
@@ -156,16 +196,29 @@ def main() -> int:
                                      group_batches=args.group_batches,
                                      schedule=G.GEER_SCHEDULE_LEARNED, model=model.handle.value)
 
-    log("plain GEER (greedy switch rule)")
-    plain = run_schedule(G, gg, ds, dt, de, dr, len(s), args.steps, args.warmup, plain_params,
-                         torch)
-    r_plain = dr.cpu().numpy()
-    log(f"plain: {plain['value']:.1f} pairs/s, {plain['ms_per_step']:.1f} ms/step")
-    log("batched + learned schedule")
-    learned = run_schedule(G, gg, ds, dt, de, dr, len(s), args.steps, args.warmup, learned_params,
-                           torch)
-    r_learned = dr.cpu().numpy()
-    log(f"learned: {learned['value']:.1f} pairs/s, {learned['ms_per_step']:.1f} ms/step")
+    plain = learned = None
+    if args.only in ("both", "plain"):
+        log("plain GEER (greedy switch rule)")
+        plain = run_schedule(G, gg, ds, dt, de, dr, len(s), args.steps, args.warmup, plain_params,
+                             torch)
+        r_plain = dr.cpu().numpy()
+        log(f"plain: {plain['value']:.1f} pairs/s, {plain['ms_per_step']:.1f} ms/step")
+    if args.only in ("both", "learned"):
+        log("batched + learned schedule")
+        learned = run_schedule(G, gg, ds, dt, de, dr, len(s), args.steps, args.warmup,
+                               learned_params, torch)
+        r_learned = dr.cpu().numpy()
+        log(f"learned: {learned['value']:.1f} pairs/s, {learned['ms_per_step']:.1f} ms/step")
+    if args.only != "both":
+        # profiling run: one schedule, nothing else launched after the timed steps
+        head = learned or plain
+        roof, table = roofline_of(head["profile"], args.steps)
+        print(json.dumps({"metric": METRIC, "value": round(head["value"], 2),
+                          "unit": "query pairs/s", "only": args.only, "steps": args.steps,
+                          "ms_per_step": round(head["ms_per_step"], 3), "roofline": roof,
+                          "kernels": table}), flush=True)
+        gg.close()
+        return 0
     _, st_l = G.geer_query(gg.handle, s, t, args.eps, learned_params(), stats=True)
     _, st_p = G.geer_query(gg.handle, s, t, args.eps, plain_params(), stats=True)
     head = learned
@@ -203,6 +256,7 @@ def main() -> int:
                     "walk_steps": int((2 * st_l["walk_pairs"] * (st_l["ell"] - st_l["ell_b"])).sum()),
                     "max_abs_diff_vs_plain": round(float(np.max(np.abs(r_learned - r_plain))), 5)},
         "autotune": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in tune.items()},
+        "spmm_roofline": spmm_roofline(head["profile"]),
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                         for kk, vv in v.items()} for k, v in table.items()},
     }
