@@ -121,11 +121,21 @@ enum {
 /* Fill *p with the defaults listed above. */
 geer_status geer_params_default(geer_params *p);
 
+/* geer_graph_create flags */
+enum {
+    GEER_GRAPH_TRUSTED = 1u << 0,          /* skip the canonical-form and connectivity checks */
+    GEER_GRAPH_WIDE_WALK_RECORDS = 1u << 1 /* 16-byte walk records even where 8 bytes fit */
+};
+
 /* Copy a canonical CSR graph to the current HIP device.
  * n: node count (>= 2).  row_ptr: host int32[n+1], row_ptr[0] == 0, non-decreasing.
- * col_idx: host int32[row_ptr[n]].  flags: 0, or 1 to skip the O(nnz log d)
- * canonical-form and connectivity checks (the caller vouches for them).
- * Returns GEER_E_GRAPH / GEER_E_NOT_CONNECTED for invalid input. */
+ * col_idx: host int32[row_ptr[n]].  flags: GEER_GRAPH_* (0 for defaults);
+ * GEER_GRAPH_TRUSTED skips the O(nnz log d) canonical-form and connectivity
+ * checks (the caller vouches for them).  Besides the CSR the device copy holds
+ * one walk record per CSR entry (neighbour, its row start and its degree):
+ * 8 bytes when the bit widths of n, nnz and the largest degree add up to at
+ * most 64, else 16 bytes.  Returns GEER_E_GRAPH / GEER_E_NOT_CONNECTED for
+ * invalid input, GEER_E_INVALID_ARG for unknown flags. */
 geer_status geer_graph_create(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
                               uint32_t flags, geer_graph **out);
 

@@ -16,6 +16,17 @@ template <class T> struct Val2;
 template <> struct Val2<float> { using type = float2; };
 template <> struct Val2<double> { using type = double2; };
 
+// Largest row (of s or t) for which the one-hop vectors are evaluated from
+// the graph instead of read from the vector buffer: on N(s) the hop-1 vector
+// is 1/d(u), elsewhere 0, so membership in the (cache-resident) sorted row of
+// s gives the same value as the random read of the buffer.
+constexpr int32_t kMemberRowMax = 64;
+
+__device__ __forceinline__ bool one_hop_from_graph(int32_t lb, int32_t ds, int32_t dt)
+{
+    return lb == 1 && ds <= kMemberRowMax && dt <= kMemberRowMax;
+}
+
 // ----------------------------------------------------------------------------
 // plan: chunk prefix sums for batch `round` of the active queries of a group
 // ----------------------------------------------------------------------------
@@ -24,11 +35,12 @@ __global__ __launch_bounds__(1024) void k_amc_plan(QState qs, int64_t q0, int nq
                                                    int64_t *__restrict__ chunk_off,
                                                    int64_t *__restrict__ total,
                                                    int32_t *__restrict__ overflow,
-                                                   int64_t *__restrict__ steps)
+                                                   int64_t *__restrict__ steps,
+                                                   const int32_t *__restrict__ row_ptr)
 {
     __shared__ int64_t s_sum[1024];
-    __shared__ unsigned long long s_steps;
-    if (threadIdx.x == 0) s_steps = 0;
+    __shared__ unsigned long long s_steps, s_vsteps;
+    if (threadIdx.x == 0) s_steps = s_vsteps = 0;
     __syncthreads();
     const int tid = threadIdx.x;
     const int per = (nq + 1023) / 1024;
@@ -40,7 +52,12 @@ __global__ __launch_bounds__(1024) void k_amc_plan(QState qs, int64_t q0, int nq
             int64_t eta = qs.eta1[q] << round;
             if (eta >= (int64_t(1) << 32)) *overflow = 1;
             local += (eta + kPairsPerChunk - 1) / kPairsPerChunk;
-            atomicAdd(&s_steps, (unsigned long long)(2 * eta * qs.lf[q]));
+            const unsigned long long st = (unsigned long long)(2 * eta * qs.lf[q]);
+            atomicAdd(&s_steps, st);
+            const int32_t s = qs.s[q], t = qs.t[q];
+            if (qs.vec_off[q] >= 0 &&
+                !one_hop_from_graph(qs.lb[q], row_ptr[s + 1] - row_ptr[s], row_ptr[t + 1] - row_ptr[t]))
+                atomicAdd(&s_vsteps, st);
         }
     }
     s_sum[tid] = local;
@@ -64,7 +81,8 @@ __global__ __launch_bounds__(1024) void k_amc_plan(QState qs, int64_t q0, int nq
     if (tid == 1023) {
         chunk_off[nq] = s_sum[1023];
         *total = s_sum[1023];
-        *steps = (int64_t)s_steps;
+        steps[0] = (int64_t)s_steps;
+        steps[1] = (int64_t)s_vsteps;
     }
 }
 
@@ -72,54 +90,123 @@ __global__ __launch_bounds__(1024) void k_amc_plan(QState qs, int64_t q0, int nq
 // walks
 // ----------------------------------------------------------------------------
 
-template <class T>
+// Walk records (one per CSR entry, see geer_graph::d_walk_rec): 8-byte
+// packed {v | b << sb | d << sd} when the bit widths of n, nnz and the largest
+// degree fit 64 bits, else 16-byte {v, b, d, -}.
+template <int RB> struct WalkRec;
+template <> struct WalkRec<8> {
+    static __device__ __forceinline__ void load(const void *rec, int64_t e, uint32_t sb,
+                                                uint32_t sd, int32_t &v, int32_t &b, int32_t &d)
+    {
+        const uint64_t x = static_cast<const uint64_t *>(rec)[e];
+        v = (int32_t)(x & ((1ull << sb) - 1));
+        b = (int32_t)((x >> sb) & ((1ull << (sd - sb)) - 1));
+        d = (int32_t)(x >> sd);
+    }
+};
+template <> struct WalkRec<16> {
+    static __device__ __forceinline__ void load(const void *rec, int64_t e, uint32_t, uint32_t,
+                                                int32_t &v, int32_t &b, int32_t &d)
+    {
+        const int4 x = static_cast<const int4 *>(rec)[e];
+        v = x.x;
+        b = x.y;
+        d = x.z;
+    }
+};
+
+// x in the sorted row held in LDS (kMemberRowMax entries, padded with INT32_MAX)
+__device__ __forceinline__ bool lds_row_contains(const int32_t *row, int32_t x)
+{
+    int pos = 0;
+#pragma unroll
+    for (int step = kMemberRowMax / 2; step > 0; step >>= 1)
+        if (row[pos + step - 1] < x) pos += step;
+    return row[pos] == x;
+}
+
+// Groups up to this many pairs keep their chunk offsets in LDS.
+constexpr int kChunkOffLds = 1024;
+
+template <class T, int RB>
 __global__ __launch_bounds__(256) void k_walk(QState qs, int64_t q0, int nq, int round,
                                               const int64_t *__restrict__ chunk_off,
                                               const int64_t *__restrict__ total_p,
                                               const int32_t *__restrict__ row_ptr,
                                               const int32_t *__restrict__ col_idx,
-                                              const T *__restrict__ pool, uint32_t key0,
-                                              uint32_t key1, int64_t qid_offset,
+                                              const void *__restrict__ rec, uint32_t rec_sb,
+                                              uint32_t rec_sd, const T *__restrict__ pool,
+                                              uint32_t key0, uint32_t key1, int64_t qid_offset,
                                               double2 *__restrict__ zpart)
 {
     using T2 = typename Val2<T>::type;
+    __shared__ int64_t s_off[kChunkOffLds + 1];
+    // per wave: the sorted rows of s and t of its current chunk's pair
+    __shared__ int32_t s_rows[4][2][kMemberRowMax];
+    const bool lds_off = nq <= kChunkOffLds;
+    if (lds_off)
+        for (int i = threadIdx.x; i <= nq; i += blockDim.x) s_off[i] = chunk_off[i];
+    __syncthreads();
+    const int64_t *off = lds_off ? s_off : chunk_off;
     const int lane = threadIdx.x & 63;
-    const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int wv = threadIdx.x >> 6;
+    const int64_t gw = (int64_t)blockIdx.x * 4 + wv;
     const int64_t nw = (int64_t)gridDim.x * 4;
     const int64_t total = *total_p;
     const uint32_t side = lane & 1;
     for (int64_t c = gw; c < total; c += nw) {
-        // query of this chunk: largest i with chunk_off[i] <= c
+        // pair of this chunk: largest i with off[i] <= c
         int lo = 0, hi = nq;
         while (hi - lo > 1) {
             int mid = (lo + hi) >> 1;
-            if (chunk_off[mid] <= c) lo = mid;
+            if (off[mid] <= c) lo = mid;
             else hi = mid;
         }
         const int64_t q = qs.ord[q0 + lo];
         const int64_t eta = qs.eta1[q] << round;
-        const int64_t k = (c - chunk_off[lo]) * kPairsPerChunk + (lane >> 1);
+        const int64_t k = (c - off[lo]) * kPairsPerChunk + (lane >> 1);
         const bool valid = k < eta;
         const int32_t s = qs.s[q], t = qs.t[q];
         const int32_t lf = qs.lf[q];
         const int64_t voff = qs.vec_off[q];
-        const double ids = 1.0 / (row_ptr[s + 1] - row_ptr[s]);
-        const double idt = 1.0 / (row_ptr[t + 1] - row_ptr[t]);
+        const int32_t bs = row_ptr[s], ds = row_ptr[s + 1] - bs;
+        const int32_t bt = row_ptr[t], dt = row_ptr[t + 1] - bt;
+        const double ids = 1.0 / ds, idt = 1.0 / dt;
+        // one-hop vectors: s*(u) = 1/d(u) on N(s), t*(u) = 1/d(u) on N(t)
+        // (the values the hop-1 scatter stored), evaluated from the graph
+        const bool member = voff >= 0 && one_hop_from_graph(qs.lb[q], ds, dt);
+        if (member) {
+            // the wave's previous reads of s_rows have completed (their values
+            // were consumed), so the rows can be overwritten in place
+            s_rows[wv][0][lane] = lane < ds ? col_idx[bs + lane] : INT32_MAX;
+            s_rows[wv][1][lane] = lane < dt ? col_idx[bt + lane] : INT32_MAX;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
         const uint32_t qid = (uint32_t)(q + qid_offset);
         const uint32_t c2 = ((uint32_t)round << 1) | side;
         double acc = 0.0;
         if (valid) {
             int32_t u = side ? t : s;
+            int32_t b = side ? bt : bs, d = side ? dt : ds;
             uint4 r4 = make_uint4(0, 0, 0, 0);
             for (int32_t step = 0; step < lf; ++step) {
                 if ((step & 3) == 0)
                     r4 = philox4x32_10(make_uint4((uint32_t)step >> 2, (uint32_t)k, c2, qid),
                                        key0, key1);
-                u = walk_next(row_ptr, col_idx, u, pick_word(r4, (uint32_t)step & 3u));
+                // the next node is row u's (draw mod d(u))-th entry; its record
+                // also carries that node's row start and degree
+                const int64_t e = b + (int32_t)(pick_word(r4, (uint32_t)step & 3u) % (uint32_t)d);
+                WalkRec<RB>::load(rec, e, rec_sb, rec_sd, u, b, d);
                 double xv, yv;
                 if (voff < 0) {
                     xv = u == s ? 1.0 : 0.0;
                     yv = u == t ? 1.0 : 0.0;
+                } else if (member) {
+                    const double inv = (double)(T)(1.0 / (double)d);
+                    xv = lds_row_contains(s_rows[wv][0], u) ? inv : 0.0;
+                    yv = lds_row_contains(s_rows[wv][1], u) ? inv : 0.0;
                 } else {
                     T2 w = *reinterpret_cast<const T2 *>(pool + voff + (size_t)u * kCols);
                     xv = (double)w.x;
@@ -205,10 +292,10 @@ geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hip
     const uint32_t key0 = (uint32_t)c.seed, key1 = (uint32_t)(c.seed >> 32);
     for (int round = 0; round < c.tau; ++round) {
         hipLaunchKernelGGL(k_amc_plan, dim3(1), dim3(1024), 0, st, c.qs, grp.q0, nq, round,
-                           chunk_off, d_total, d_over, d_steps);
+                           chunk_off, d_total, d_over, d_steps, g->d_row_ptr);
         GEER_HIP(hipGetLastError());
-        int64_t host[3] = {0, 0, 0};
-        GEER_HIP(hipMemcpyAsync(host, d_total, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        int64_t host[4] = {0, 0, 0, 0};
+        GEER_HIP(hipMemcpyAsync(host, d_total, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
         GEER_HIP(hipStreamSynchronize(st));
         if (((int32_t *)&host[1])[0] != 0)
             return fail(GEER_E_INVALID_ARG, "AMC batch exceeds 2^32 walk pairs for a query");
@@ -217,20 +304,27 @@ geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hip
         GEER_TRY(ws.zpart.reserve((size_t)total * sizeof(double2)));
         const int64_t want_blocks = (total + 3) / 4;
         const int blocks = (int)std::min<int64_t>(want_blocks, (int64_t)g->num_cus * 16);
-        const double steps = (double)host[2];
+        const double steps = (double)host[2], vsteps = (double)host[3];
         int tok = prof_begin(g, st);
-        if (grp.value_size == 4)
-            hipLaunchKernelGGL(k_walk<float>, dim3(blocks), dim3(256), 0, st, c.qs, grp.q0, nq,
-                               round, chunk_off, d_total, g->d_row_ptr, g->d_col_idx,
-                               (const float *)grp.pool, key0, key1, c.qid_offset,
-                               ws.zpart.as<double2>());
-        else
-            hipLaunchKernelGGL(k_walk<double>, dim3(blocks), dim3(256), 0, st, c.qs, grp.q0, nq,
-                               round, chunk_off, d_total, g->d_row_ptr, g->d_col_idx,
-                               (const double *)grp.pool, key0, key1, c.qid_offset,
-                               ws.zpart.as<double2>());
-        // per step: row offsets of u (8 B), one column index (4 B), the pair's two values (8 B)
-        prof_end(g, tok, PK_WALK, 20.0 * steps, steps, st);
+        const void *rec = g->d_walk_rec;
+        const uint32_t sb = (uint32_t)g->rec_sb, sd = (uint32_t)g->rec_sd;
+        auto *zp = ws.zpart.as<double2>();
+#define GEER_WALK_LAUNCH(T, RB)                                                                 \
+    hipLaunchKernelGGL((k_walk<T, RB>), dim3(blocks), dim3(256), 0, st, c.qs, grp.q0, nq, round, \
+                       chunk_off, d_total, g->d_row_ptr, g->d_col_idx, rec, sb, sd,             \
+                       (const T *)grp.pool, key0, key1, c.qid_offset, zp)
+        if (grp.value_size == 4) {
+            if (g->walk_rec_bytes == 8) GEER_WALK_LAUNCH(float, 8);
+            else GEER_WALK_LAUNCH(float, 16);
+        } else {
+            if (g->walk_rec_bytes == 8) GEER_WALK_LAUNCH(double, 8);
+            else GEER_WALK_LAUNCH(double, 16);
+        }
+#undef GEER_WALK_LAUNCH
+        // per step: one walk record; steps of pairs whose vectors are read
+        // also fetch the pair's two values at the new node
+        prof_end(g, tok, PK_WALK, (double)g->walk_rec_bytes * steps + 2.0 * grp.value_size * vsteps,
+                 steps, st);
         GEER_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_amc_stop, dim3((nq + 3) / 4), dim3(256), 0, st, c.qs, grp.q0, nq,
                            round, chunk_off, ws.zpart.as<double2>(), c.tau, c.delta);

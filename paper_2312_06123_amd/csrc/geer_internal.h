@@ -141,6 +141,14 @@ struct geer_graph {
     int32_t *d_col_idx = nullptr;
     float *d_inv_deg_f = nullptr;
     double *d_inv_deg_d = nullptr;
+    // walk records, one per CSR entry e with v = col_idx[e], carrying v, its
+    // row start b = row_ptr[v] and degree d, so that a walk step reads one
+    // record instead of col_idx and row_ptr: 8 bytes packed as
+    // v | b << rec_sb | d << rec_sd when the bit widths fit, else int4 {v, b, d, 0}
+    void *d_walk_rec = nullptr;
+    int walk_rec_bytes = 16;
+    bool wide_records = false;             // GEER_GRAPH_WIDE_WALK_RECORDS
+    int rec_sb = 0, rec_sd = 0;
     // SpMM work decomposition: light rows (degree <= kSegNnz) sorted by
     // degree descending, heavy rows split into segments of <= kSegNnz entries
     int32_t *d_light_rows = nullptr;

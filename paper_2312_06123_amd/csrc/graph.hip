@@ -155,6 +155,29 @@ template <class T> static geer_status upload(T **dst, const T *src, size_t count
     return GEER_OK;
 }
 
+__global__ void k_walk_records(int64_t nnz, const int32_t *__restrict__ row_ptr,
+                               const int32_t *__restrict__ col_idx, int packed, uint32_t sb,
+                               uint32_t sd, void *__restrict__ rec)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = col_idx[e];
+        const int32_t b = row_ptr[v], d = row_ptr[v + 1] - b;
+        if (packed)
+            static_cast<uint64_t *>(rec)[e] =
+                (uint64_t)v | ((uint64_t)b << sb) | ((uint64_t)d << sd);
+        else
+            static_cast<int4 *>(rec)[e] = make_int4(v, b, d, 0);
+    }
+}
+
+static int bit_width(uint64_t x)
+{
+    int k = 0;
+    while (k < 64 && (1ull << k) <= x) ++k;
+    return k;
+}
+
 static geer_status build_graph(geer_graph *g, const int32_t *rp, const int32_t *ci)
 {
     const int32_t n = g->n;
@@ -192,6 +215,24 @@ static geer_status build_graph(geer_graph *g, const int32_t *rp, const int32_t *
     g->fx_shift = 62 - bits;
     GEER_TRY(upload(&g->d_inv_deg_f, invf.data(), invf.size()));
     GEER_TRY(upload(&g->d_inv_deg_d, invd.data(), invd.size()));
+    {
+        const int bv = std::max(1, bit_width((uint64_t)(n - 1)));
+        const int bb = std::max(1, bit_width((uint64_t)std::max<int64_t>(g->nnz - 1, 0)));
+        const int bd = bit_width((uint64_t)maxd);
+        const bool packed = !g->wide_records && bv + bb + bd <= 64;
+        g->walk_rec_bytes = packed ? 8 : 16;
+        g->rec_sb = bv;
+        g->rec_sd = bv + bb;
+    }
+    GEER_HIP(hipMalloc(&g->d_walk_rec, std::max<int64_t>(g->nnz, 1) * g->walk_rec_bytes));
+    if (g->nnz) {
+        const int64_t blocks = std::min<int64_t>((g->nnz + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_walk_records, dim3((unsigned)blocks), dim3(256), 0, g->stream,
+                           g->nnz, g->d_row_ptr, g->d_col_idx, g->walk_rec_bytes == 8 ? 1 : 0,
+                           (uint32_t)g->rec_sb, (uint32_t)g->rec_sd, g->d_walk_rec);
+        GEER_HIP(hipGetLastError());
+        GEER_HIP(hipStreamSynchronize(g->stream));
+    }
 
     // light rows sorted by degree descending (long rows first for load balance),
     // heavy rows split into consecutive segments of at most kSegNnz entries
@@ -241,9 +282,12 @@ geer_status geer_graph_create(int32_t n, const int32_t *row_ptr, const int32_t *
     if (n < 2) return fail(GEER_E_INVALID_ARG, "n must be >= 2");
     if (!row_ptr || !col_idx) return fail(GEER_E_INVALID_ARG, "row_ptr/col_idx is NULL");
     if (row_ptr[n] < 0) return fail(GEER_E_GRAPH, "row_ptr[n] is negative");
-    if (!(flags & 1u)) GEER_TRY(validate_csr(n, row_ptr, col_idx));
+    if (flags & ~(uint32_t)(GEER_GRAPH_TRUSTED | GEER_GRAPH_WIDE_WALK_RECORDS))
+        return fail(GEER_E_INVALID_ARG, "unknown graph flags");
+    if (!(flags & GEER_GRAPH_TRUSTED)) GEER_TRY(validate_csr(n, row_ptr, col_idx));
     geer_graph *g = new geer_graph();
     g->n = n;
+    g->wide_records = (flags & GEER_GRAPH_WIDE_WALK_RECORDS) != 0;
     g->nnz = row_ptr[n];
     if (hipGetDevice(&g->device) != hipSuccess) {
         delete g;
@@ -276,7 +320,7 @@ void geer_graph_destroy(geer_graph *g)
     if (g->stream) (void)hipStreamSynchronize(g->stream);
     void *ptrs[] = {g->d_row_ptr,    g->d_col_idx,    g->d_inv_deg_f,       g->d_inv_deg_d,
                     g->d_light_rows, g->d_heavy_rows, g->d_heavy_seg_start, g->d_seg_begin,
-                    g->d_seg_end,    g->d_nbr_work,   g->d_min_nbr_deg};
+                    g->d_seg_end,    g->d_nbr_work,   g->d_min_nbr_deg,     g->d_walk_rec};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     DevBuf *bufs[] = {&g->ws.pool,    &g->ws.bits,   &g->ws.part,      &g->ws.segbuf,

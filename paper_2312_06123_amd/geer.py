@@ -29,6 +29,9 @@ GEER_SCHEDULE_GREEDY = 0
 GEER_SCHEDULE_LEARNED = 1
 GEER_SCHEDULE_FIXED = 2
 
+GEER_GRAPH_TRUSTED = 1
+GEER_GRAPH_WIDE_WALK_RECORDS = 2
+
 GEER_FLAG_FP64_VECTORS = 1
 GEER_FLAG_NO_GRAPH_CAPTURE = 2
 

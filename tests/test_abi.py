@@ -69,6 +69,10 @@ def test_graph_create_argument_errors():
     with pytest.raises(G.GeerError) as e:
         G.geer_graph_create(1, np.array([0, 0], np.int32), np.zeros(0, np.int32))
     assert e.value.status == G.GEER_E_INVALID_ARG
+    rp, ci = _csr(2, [[1], [0]])
+    with pytest.raises(G.GeerError) as e:
+        G.geer_graph_create(2, rp, ci, flags=4)
+    assert e.value.status == G.GEER_E_INVALID_ARG
 
 
 def test_generators_are_canonical_and_seeded():

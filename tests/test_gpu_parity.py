@@ -148,7 +148,7 @@ def test_geer_fp64_matches_checker(er_graph):
     assert np.all(np.abs(r[agree] - ro[agree]) <= 1e-9)
 
 
-@pytest.mark.parametrize("schedule", ["greedy", "amc_only", "smm_only", "fixed2"])
+@pytest.mark.parametrize("schedule", ["greedy", "amc_only", "smm_only", "fixed1", "fixed2"])
 def test_geer_fp32_coverage_and_replay(cl_graph, schedule):
     g, lam = cl_graph
     s, t = I.uniform_pairs(g.n, 200, 12)
@@ -156,7 +156,7 @@ def test_geer_fp32_coverage_and_replay(cl_graph, schedule):
     kw = {}
     okw = {"schedule": "greedy"}
     if schedule != "greedy":
-        lb = {"amc_only": 0, "smm_only": 10000, "fixed2": 2}[schedule]
+        lb = {"amc_only": 0, "smm_only": 10000, "fixed1": 1, "fixed2": 2}[schedule]
         kw["fixed_ell_b"] = lb
         okw = {"schedule": "fixed", "fixed_lb": lb}
     with _graph(g, lam) as gg:
@@ -172,6 +172,24 @@ def test_geer_fp32_coverage_and_replay(cl_graph, schedule):
     if schedule == "smm_only":
         assert np.all(st["walk_pairs"] == 0)
         assert np.all(np.abs(r - ex) <= eps / 2 + 1e-5)
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_geer_walk_record_widths_identical(cl_graph, fp64):
+    # 8-byte packed and 16-byte walk records describe the same walks: every
+    # answer and every statistic is bit-identical
+    g, lam = cl_graph
+    s, t = I.uniform_pairs(g.n, 300, 21)
+    s[:40], t[:40] = I.edge_pairs(g, 40, 22)
+    p = G.geer_params_default(seed=31, flags=G.GEER_FLAG_FP64_VECTORS if fp64 else 0)
+    out = []
+    for flags in (0, G.GEER_GRAPH_WIDE_WALK_RECORDS):
+        with G.Graph(g.n, g.row_ptr32(), g.col_idx, flags=flags, lam=lam) as gg:
+            out.append(G.geer_query(gg.handle, s, t, 0.1, p, stats=True))
+    (r8, st8), (r16, st16) = out
+    assert np.array_equal(r8, r16)
+    for f in ("ell", "ell_b", "eta1", "batches_run", "walk_pairs"):
+        assert np.array_equal(st8[f], st16[f]), f
 
 
 def test_geer_edge_cases(er_graph):
