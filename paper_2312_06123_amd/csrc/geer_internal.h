@@ -72,16 +72,17 @@ struct Workspace {
     DevBuf bits;      // structural supports: slots x {H1, A, B} x n x kBitWords
     DevBuf part;      // per-block column statistics (max1, max2 as double; degree sums)
     DevBuf segbuf;    // heavy-row segment partial sums (values + bits)
-    DevBuf colstat;   // per-column reduced statistics for the current hop
+    DevBuf colstat;   // per slot: per-column reduced statistics of the current hop
+    DevBuf hpart;     // per slot: hop-2 partial column statistics (kPushSplit rows)
     DevBuf qstate;    // QState arrays
     DevBuf chunk_off; // AMC: chunk prefix sums per group query
     DevBuf zpart;     // AMC: per-chunk (sum Z, sum Z^2)
     DevBuf misc;      // small scalars (active masks, totals)
     DevBuf io;        // staging for host inputs/outputs
-    DevBuf acc;       // sparse hop: n x kCols fixed-point accumulators (kept all zero)
+    DevBuf acc;       // sparse hop 2: per slot n x kCols fixed-point accumulators (kept all zero)
     DevBuf meta;      // per-slot masks (active, hop-2 cleanup, hop-2 paths, static levels)
     DevBuf feat;      // learned scheduler: per-pair features
-    bool acc_zeroed = false;
+    int acc_slots = 0;          // slots of all-zero accumulators held in acc
     std::vector<char> a_dirty;  // per slot: buffer A was written by a dense hop
     int slots = 0;
     int value_size = 0;
@@ -254,6 +255,51 @@ __host__ __device__ inline double bernstein_of(double nz, double var, double psi
 // Kernel launchers (defined in smm.hip / amc.hip)
 // ----------------------------------------------------------------------------
 
+constexpr int kPushSplit = 8;       // blocks per column of the global sparse hop 2
+constexpr int kHashLoadMax = 9830;  // columns with more hop-2 work use the global path
+
+// Where the batches of a group live.  Batch k of the group holds the pairs at
+// positions [p0 + k B, min(p0 + (k+1) B, pend)) of qs.ord and owns slot k:
+// three n x kCols value buffers (H1, A, B) with their support bits, per-column
+// statistics and mask words.  Kernels that cover a whole group take the slot
+// from the grid.
+struct SlotArgs {
+    int64_t p0, pend;
+    int32_t B;
+    int32_t G;            // slots of the mask-word layout below
+    char *pool;           // value buffers, slot-major
+    uint32_t *bits;       // support bits, same layout with kBitWords per node
+    int64_t buf_elems;    // n * kCols
+    int64_t buf_words;    // n * kBitWords
+    double *cs;           // per slot: m1[kCols], m2[kCols], sd[kCols] (int64)
+    double *hpart;        // per slot: m1, m2, sd, each kPushSplit x kCols
+    uint64_t *meta;       // [0,G) active masks, [G,2G) hop-2 masks, [2G,6G) hop-2 paths
+};
+
+__host__ __device__ inline int64_t slot_q0(const SlotArgs &a, int k) { return a.p0 + (int64_t)k * a.B; }
+__host__ __device__ inline int slot_nb(const SlotArgs &a, int k)
+{
+    const int64_t r = a.pend - slot_q0(a, k);
+    return (int)(r < a.B ? (r > 0 ? r : 0) : a.B);
+}
+__host__ __device__ inline int64_t slot_elem_off(const SlotArgs &a, int k, int which)
+{
+    return ((int64_t)k * 3 + which) * a.buf_elems;
+}
+template <class T> __host__ __device__ inline T *slot_buf(const SlotArgs &a, int k, int which)
+{
+    return reinterpret_cast<T *>(a.pool) + slot_elem_off(a, k, which);
+}
+__host__ __device__ inline uint32_t *slot_bits(const SlotArgs &a, int k, int which)
+{
+    return a.bits + ((int64_t)k * 3 + which) * a.buf_words;
+}
+__host__ __device__ inline double *slot_cs(const SlotArgs &a, int k) { return a.cs + (size_t)k * 3 * kCols; }
+__host__ __device__ inline double *slot_hpart(const SlotArgs &a, int k)
+{
+    return a.hpart + (size_t)k * 3 * kPushSplit * kCols;
+}
+
 struct HopArgs {
     const void *in;          // n x kCols values (previous hop)
     void *out;               // n x kCols values (this hop)
@@ -261,6 +307,7 @@ struct HopArgs {
     uint32_t *out_bits;
     const uint64_t *mask;    // active pairs of the batch (bit j = pair j)
     uint64_t host_mask;      // the same mask as seen by the host (for byte accounting)
+    double *cs;              // column statistics of the batch's slot
     int col0, col_tile;      // column slice of this launch
 };
 
@@ -276,21 +323,25 @@ struct QueryCtx {
 
 geer_status launch_init_queries(geer_graph *g, const QueryCtx &c, const int32_t *d_fixed,
                                 int32_t forced_hops, hipStream_t st);
-geer_status launch_hop1(geer_graph *g, const QueryCtx &c, int64_t q0, int nb, void *h1,
-                        uint32_t *h1_bits, const uint64_t *mask, int value_size, bool clear,
-                        hipStream_t st);
+// hop 1 (or, with clear, its reset) for slots [0, nslots)
+geer_status launch_hop1_group(geer_graph *g, const QueryCtx &c, const SlotArgs &sa, int nslots,
+                              bool clear, hipStream_t st);
 geer_status launch_hop_dense(geer_graph *g, const HopArgs &a, int value_size, hipStream_t st);
-geer_status launch_epilogue(geer_graph *g, const QueryCtx &c, int64_t q0, int nb, int hop,
-                            const void *vec, int64_t vec_elem_off, uint64_t *mask,
-                            int value_size, int dense, hipStream_t st);
-geer_status launch_hop2_sparse(geer_graph *g, const QueryCtx &c, int64_t q0, const uint64_t *mask,
-                               void *out, uint32_t *out_bits, int value_size, int mode,
-                               hipStream_t st);
+// epilogue of hop `hop` (vectors in buffer `which`) for slots [0, nslots)
+geer_status launch_epilogue_group(geer_graph *g, const QueryCtx &c, const SlotArgs &sa,
+                                  int nslots, int hop, int which, int value_size, hipStream_t st);
+// global-path sparse hop 2, slots [slot0, slot0 + nslots): mode 0 push,
+// 1 convert (+ statistics into the slot's hop-2 partials), 2 clear
+geer_status launch_hop2_sparse(geer_graph *g, const QueryCtx &c, const SlotArgs &sa, int slot0,
+                               int nslots, int value_size, int mode, hipStream_t st);
 geer_status launch_zero(geer_graph *g, void *p, size_t bytes, hipStream_t st);
-geer_status launch_hop2_lds(geer_graph *g, const QueryCtx &c, int64_t q0, const uint64_t *mask,
-                            void *out, uint32_t *out_bits, int value_size, hipStream_t st);
-geer_status launch_colstat(geer_graph *g, const uint64_t *mask, int prows, hipStream_t st);
-constexpr int kHashLoadMax = 9830;  // columns with more hop-2 work use the global path
+// make at least min(want, what fits) slots of hop-2 accumulators available;
+// returns the slot count (0 with *err set on failure)
+int ensure_hop2_acc(geer_graph *g, int want, hipStream_t st, geer_status *err);
+geer_status launch_hop2_lds_group(geer_graph *g, const QueryCtx &c, const SlotArgs &sa,
+                                  int nslots, int value_size, hipStream_t st);
+// hop-2 partials -> column statistics for the pairs in each slot's hop-2 mask
+geer_status launch_colstat_group(geer_graph *g, const SlotArgs &sa, int nslots, hipStream_t st);
 geer_status launch_column_top2(geer_graph *g, const void *vec, int ncols, int value_size,
                                hipStream_t st);
 

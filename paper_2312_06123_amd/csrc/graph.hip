@@ -326,7 +326,7 @@ void geer_graph_destroy(geer_graph *g)
     DevBuf *bufs[] = {&g->ws.pool,    &g->ws.bits,   &g->ws.part,      &g->ws.segbuf,
                       &g->ws.colstat, &g->ws.qstate, &g->ws.chunk_off, &g->ws.zpart,
                       &g->ws.misc,    &g->ws.io,     &g->ws.acc,       &g->ws.meta,
-                      &g->ws.feat};
+                      &g->ws.feat,    &g->ws.hpart};
     for (DevBuf *b : bufs) b->release();
     for (ProfRec &r : g->prof.recs) {
         (void)hipEventDestroy(r.a);

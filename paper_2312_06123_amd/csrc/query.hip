@@ -76,15 +76,42 @@ geer_status ensure_slots(geer_graph *g, int slots, int value_size)
         ws.a_dirty.assign(slots, 0);
     }
     if ((int)ws.a_dirty.size() < slots) ws.a_dirty.resize(slots, 0);
+    GEER_TRY(ws.colstat.reserve((size_t)std::max(slots, 1) * kCols * (2 * sizeof(double) + sizeof(int64_t))));
+    GEER_TRY(ws.hpart.reserve((size_t)std::max(slots, 1) * 3 * kPushSplit * kCols * sizeof(double)));
     return GEER_OK;
 }
 
-__global__ void k_batch_mask(QState qs, int64_t q0, int nb, uint64_t *mask)
+// Active-pair mask of every batch of a group (block k -> mask word k).
+__global__ void k_batch_mask(QState qs, SlotArgs sa)
 {
-    const int j = threadIdx.x;
-    bool a = j < nb && qs.active_smm[qs.ord[q0 + j]];
-    unsigned long long m = __ballot(a);
-    if (j == 0) *mask = m;
+    const int k = blockIdx.x, j = threadIdx.x;
+    const bool a = j < slot_nb(sa, k) && qs.active_smm[qs.ord[slot_q0(sa, k) + j]];
+    const unsigned long long m = __ballot(a);
+    if (j == 0) sa.meta[k] = m;
+}
+
+// Small host-computed mask words go to the device as kernel arguments: no
+// pageable-memory copy whose source must outlive the call, and nothing that
+// stream capture could not record.
+struct Words64 {
+    uint64_t w[64];
+};
+
+__global__ void k_set_words(uint64_t *__restrict__ dst, int n, Words64 v)
+{
+    if ((int)threadIdx.x < n) dst[threadIdx.x] = v.w[threadIdx.x];
+}
+
+static geer_status set_words(uint64_t *dst, const uint64_t *src, size_t n, hipStream_t st)
+{
+    for (size_t i = 0; i < n; i += 64) {
+        Words64 v;
+        const int m = (int)std::min<size_t>(64, n - i);
+        std::memcpy(v.w, src + i, m * sizeof(uint64_t));
+        hipLaunchKernelGGL(k_set_words, dim3(1), dim3(64), 0, st, dst + i, m, v);
+        GEER_HIP(hipGetLastError());
+    }
+    return GEER_OK;
 }
 
 struct SlotView {
@@ -100,35 +127,21 @@ struct SlotView {
     uint32_t *bw(int slot, int which) const { return bits + ((size_t)slot * 3 + which) * n * kBitWords; }
 };
 
-static int64_t host_mask(geer_graph *g, uint64_t *d_mask, hipStream_t st, geer_status *err)
-{
-    uint64_t m = 0;
-    if (hipMemcpyAsync(&m, d_mask, sizeof(m), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess) {
-        *err = fail(GEER_E_DEVICE, "reading the batch mask failed");
-        return 0;
-    }
-    (void)g;
-    return (int64_t)m;
-}
-
 // What a batch left in its slot (needed to restore the all-zero state of the
 // sparse buffers after the group's AMC phase).
 struct BatchRec {
-    int64_t q0 = 0;
-    int nb = 0;
     bool hop1 = false;          // H1 holds scattered entries
     uint64_t hop2_sparse = 0;   // pairs whose hop-2 vectors were pushed into A
 };
 
-// Per-slot device words: [0,G) active mask, [G,2G) hop-2 cleanup mask,
-// [2G,6G) hop-2 path masks (4 words per slot), [6G, 6G + G*L) static level masks.
+// Per-slot device words (G = slots of the layout): [0,G) active masks,
+// [G,2G) hop-2 masks, [2G,6G) hop-2 paths (LDS columns: 2 words, global
+// columns: 2 words), [6G, 6G + G*L) static level masks.
 struct SlotMeta {
     uint64_t *base;
     int G;
     uint64_t *active(int k) const { return base + k; }
     uint64_t *h2(int k) const { return base + G + k; }
-    uint64_t *paths(int k) const { return base + 2 * G + 4 * k; }
     uint64_t *level(int k, int h, int L) const { return base + 6 * G + (size_t)k * L + h; }
 };
 
@@ -138,6 +151,23 @@ struct GroupPlan {
     int64_t pend = 0;          // end of the phase (positions)
     int B = 64;
 };
+
+static SlotArgs slot_args(geer_graph *g, const SlotView &sv, const SlotMeta &sm, const GroupPlan &gp)
+{
+    SlotArgs a;
+    a.p0 = gp.p0;
+    a.pend = gp.pend;
+    a.B = gp.B;
+    a.G = sm.G;
+    a.pool = sv.pool;
+    a.bits = sv.bits;
+    a.buf_elems = (int64_t)sv.n * kCols;
+    a.buf_words = (int64_t)sv.n * kBitWords;
+    a.cs = g->ws.colstat.as<double>();
+    a.hpart = g->ws.hpart.as<double>();
+    a.meta = sm.base;
+    return a;
+}
 
 // Column tile of one dense hop.  An explicit request wins; with measured
 // tile times the cheapest is taken for this hop's active pairs (only tiles
@@ -165,87 +195,128 @@ static int pick_tile(const geer_graph *g, int requested, uint64_t hmask, int vs)
     return pick;
 }
 
-// One hop (h >= 2) of batch k of the group.  hmask: pairs active at this hop.
-static geer_status launch_level(geer_graph *g, const QueryCtx &c, const SlotView &sv,
-                                const SlotMeta &sm, int k, int64_t q0, int nb, int hop,
-                                uint64_t hmask, const uint64_t *d_mask, uint64_t *d_clear,
-                                const int32_t *h_s, const int32_t *h_t, const int32_t *h_ord,
-                                int col_tile, BatchRec *rec, std::vector<uint64_t> &host_paths_all)
+// One hop level (hop >= 2) of the batches [0, nbat) of a group.  hm[k]: pairs
+// of batch k active at this hop; dmask[k]: the same mask on the device.
+// Hop 2 of a batch is sparse (exact push from the hop-1 frontier) when its
+// work, the neighbour-degree sums of its start nodes, is at most two passes
+// over the CSR; columns whose work fits an LDS hash table take the LDS path,
+// the others the global fixed-point path.  One launch covers every batch for
+// the LDS path, the statistics and the epilogue; dense hops run per batch.
+static geer_status run_level(geer_graph *g, const QueryCtx &c, const SlotView &sv,
+                             const SlotMeta &sm, const SlotArgs &sa, int nbat, int hop,
+                             const std::vector<uint64_t> &hm,
+                             const std::vector<const uint64_t *> &dmask, const int32_t *h_s,
+                             const int32_t *h_t, const int32_t *h_ord, int col_tile,
+                             std::vector<BatchRec> &recs)
 {
     Workspace &ws = g->ws;
+    const int L = sm.G;
     const int wout = hop % 2 == 0 ? 1 : 2;  // output buffer: A on even hops, B on odd
-    bool sparse = false;
-    uint64_t m_lds[2] = {0, 0}, m_glob[2] = {0, 0};
+    std::vector<char> sparse(nbat, 0);
     if (hop == 2 && sv.vs == 4) {
-        // hop-2 work of a column is the neighbour-degree sum of its start node
-        double work = 0.0;
-        for (int j = 0; j < nb; ++j) {
-            if (!((hmask >> j) & 1ull)) continue;
-            const int32_t q = h_ord[q0 + j];
-            for (int side = 0; side < 2; ++side) {
-                const int c2 = 2 * j + side;
-                const int64_t wk = g->h_nbr_work[side ? h_t[q] : h_s[q]];
-                work += (double)wk;
-                if (wk <= kHashLoadMax) m_lds[c2 >> 6] |= 1ull << (c2 & 63);
-                else m_glob[c2 >> 6] |= 1ull << (c2 & 63);
+        std::vector<uint64_t> words(5 * (size_t)L, 0);  // h2 masks, then paths
+        bool any = false, any_lds = false;
+        std::vector<char> glob(nbat, 0);
+        for (int k = 0; k < nbat; ++k) {
+            if (!hm[k]) continue;
+            uint64_t m_lds[2] = {0, 0}, m_glob[2] = {0, 0};
+            double work = 0.0;
+            const int64_t q0 = slot_q0(sa, k);
+            for (int j = 0; j < slot_nb(sa, k); ++j) {
+                if (!((hm[k] >> j) & 1ull)) continue;
+                const int32_t q = h_ord[q0 + j];
+                for (int side = 0; side < 2; ++side) {
+                    const int c2 = 2 * j + side;
+                    const int64_t wk = g->h_nbr_work[side ? h_t[q] : h_s[q]];
+                    work += (double)wk;
+                    if (wk <= kHashLoadMax) m_lds[c2 >> 6] |= 1ull << (c2 & 63);
+                    else m_glob[c2 >> 6] |= 1ull << (c2 & 63);
+                }
             }
+            if (work > 2.0 * (double)g->nnz) continue;
+            sparse[k] = 1;
+            any = true;
+            any_lds |= (m_lds[0] | m_lds[1]) != 0;
+            glob[k] = (m_glob[0] | m_glob[1]) != 0;
+            words[k] = hm[k];
+            uint64_t *pw = &words[L + 4 * (size_t)k];
+            pw[0] = m_lds[0];
+            pw[1] = m_lds[1];
+            pw[2] = m_glob[0];
+            pw[3] = m_glob[1];
+            prof_add_units(g, PK_HOP2_LDS, work);
         }
-        sparse = work <= 2.0 * (double)g->nnz;
-        if (sparse) prof_add_units(g, PK_HOP2_LDS, work);
+        if (any) {
+            for (int k = 0; k < nbat; ++k)
+                if (sparse[k] && ws.a_dirty[k]) {
+                    GEER_TRY(launch_zero(g, sv.buf(k, 1), (size_t)g->n * kCols * sv.vs, c.stream));
+                    GEER_TRY(launch_zero(g, sv.bw(k, 1), (size_t)g->n * kBitWords * 4, c.stream));
+                    ws.a_dirty[k] = 0;
+                }
+            GEER_TRY(set_words(sm.h2(0), words.data(), words.size(), c.stream));
+            GEER_TRY(launch_zero(g, sa.hpart, (size_t)nbat * 3 * kPushSplit * kCols * sizeof(double),
+                                 c.stream));
+            if (any_lds) GEER_TRY(launch_hop2_lds_group(g, c, sa, nbat, sv.vs, c.stream));
+            int k0 = 0, k1 = -1;  // slots with global-path columns lie in [k0, k1]
+            for (int k = nbat - 1; k >= 0; --k)
+                if (glob[k]) k0 = k;
+            for (int k = 0; k < nbat; ++k)
+                if (glob[k]) k1 = k;
+            if (k1 >= k0) {
+                geer_status err;
+                const int A = ensure_hop2_acc(g, k1 - k0 + 1, c.stream, &err);
+                GEER_TRY(err);
+                for (int a0 = k0; a0 <= k1; a0 += A) {
+                    const int na = std::min(A, k1 + 1 - a0);
+                    GEER_TRY(launch_hop2_sparse(g, c, sa, a0, na, sv.vs, 0, c.stream));
+                    GEER_TRY(launch_hop2_sparse(g, c, sa, a0, na, sv.vs, 1, c.stream));
+                }
+            }
+            GEER_TRY(launch_colstat_group(g, sa, nbat, c.stream));
+            for (int k = 0; k < nbat; ++k)
+                if (sparse[k]) recs[k].hop2_sparse = hm[k];
+        }
     }
-    if (sparse) {
-        if (ws.a_dirty[k]) {
-            GEER_TRY(launch_zero(g, sv.buf(k, 1), (size_t)g->n * kCols * sv.vs, c.stream));
-            GEER_TRY(launch_zero(g, sv.bw(k, 1), (size_t)g->n * kBitWords * 4, c.stream));
-            ws.a_dirty[k] = 0;
-        }
-        uint64_t *hp = &host_paths_all[4 * (size_t)k];
-        hp[0] = m_lds[0];
-        hp[1] = m_lds[1];
-        hp[2] = m_glob[0];
-        hp[3] = m_glob[1];
-        GEER_HIP(hipMemcpyAsync(sm.paths(k), hp, 4 * sizeof(uint64_t), hipMemcpyHostToDevice, c.stream));
-        GEER_HIP(hipMemcpyAsync(sm.h2(k), d_mask, sizeof(uint64_t), hipMemcpyDeviceToDevice, c.stream));
-        const size_t part_bytes = (size_t)8 * kCols * (2 * sizeof(double) + sizeof(int64_t));
-        GEER_TRY(ws.part.reserve(std::max(ws.part.bytes, part_bytes)));
-        GEER_TRY(launch_zero(g, ws.part.ptr, part_bytes, c.stream));
-        if (m_lds[0] | m_lds[1])
-            GEER_TRY(launch_hop2_lds(g, c, q0, sm.paths(k), sv.buf(k, 1), sv.bw(k, 1), sv.vs, c.stream));
-        if (m_glob[0] | m_glob[1]) {
-            GEER_TRY(launch_hop2_sparse(g, c, q0, sm.paths(k) + 2, sv.buf(k, 1), sv.bw(k, 1), sv.vs, 0, c.stream));
-            GEER_TRY(launch_hop2_sparse(g, c, q0, sm.paths(k) + 2, sv.buf(k, 1), sv.bw(k, 1), sv.vs, 1, c.stream));
-        }
-        GEER_TRY(launch_colstat(g, d_mask, 8, c.stream));
-        rec->hop2_sparse = hmask;
-    } else {
+    for (int k = 0; k < nbat; ++k) {
+        if (!hm[k] || sparse[k]) continue;
         const int win = hop == 2 ? 0 : (hop % 2 == 0 ? 2 : 1);
         HopArgs a;
         a.in = sv.buf(k, win);
         a.out = sv.buf(k, wout);
         a.in_bits = sv.bw(k, win);
         a.out_bits = sv.bw(k, wout);
-        a.mask = d_mask;
-        a.host_mask = hmask;
+        a.mask = dmask[k];
+        a.host_mask = hm[k];
+        a.cs = slot_cs(sa, k);
         a.col0 = 0;
-        a.col_tile = pick_tile(g, col_tile, hmask, sv.vs);
+        a.col_tile = pick_tile(g, col_tile, hm[k], sv.vs);
         GEER_TRY(launch_hop_dense(g, a, sv.vs, c.stream));
         if (wout == 1) ws.a_dirty[k] = 1;
     }
-    GEER_TRY(launch_epilogue(g, c, q0, nb, hop, sv.buf(k, wout), sv.elem_off(k, wout), d_clear, sv.vs,
-                             1, c.stream));
-    return GEER_OK;
+    return launch_epilogue_group(g, c, sa, nbat, hop, wout, sv.vs, c.stream);
 }
 
-// Restore H1 and the sparse part of A of a finished batch to zero.
-static geer_status cleanup_batch(geer_graph *g, const QueryCtx &c, const SlotView &sv,
-                                 const SlotMeta &sm, int k, const BatchRec &rec)
+// Restore H1 and the sparse part of A of the group's batches to zero.
+static geer_status cleanup_group(geer_graph *g, const QueryCtx &c, const SlotView &sv,
+                                 const SlotMeta &sm, const SlotArgs &sa, int nbat,
+                                 const std::vector<BatchRec> &recs)
 {
-    if (rec.hop1)
-        GEER_TRY(launch_hop1(g, c, rec.q0, rec.nb, sv.buf(k, 0), sv.bw(k, 0), nullptr, sv.vs, true,
-                             c.stream));
-    if (rec.hop2_sparse && !g->ws.a_dirty[k])
-        GEER_TRY(launch_hop2_sparse(g, c, rec.q0, sm.h2(k), sv.buf(k, 1), sv.bw(k, 1), sv.vs, 2,
-                                    c.stream));
+    bool h1 = false, h2 = false;
+    std::vector<uint64_t> words(nbat, 0);
+    for (int k = 0; k < nbat; ++k) {
+        h1 |= recs[k].hop1;
+        // a dense hop that wrote A later makes it dirty: it is zeroed in full
+        // before its next sparse use instead
+        if (recs[k].hop2_sparse && !g->ws.a_dirty[k]) {
+            words[k] = recs[k].hop2_sparse;
+            h2 = true;
+        }
+    }
+    if (h1) GEER_TRY(launch_hop1_group(g, c, sa, nbat, true, c.stream));
+    if (h2) {
+        GEER_TRY(set_words(sm.h2(0), words.data(), words.size(), c.stream));
+        GEER_TRY(launch_hop2_sparse(g, c, sa, 0, nbat, sv.vs, 2, c.stream));
+    }
     return GEER_OK;
 }
 
@@ -258,77 +329,60 @@ static geer_status smm_group(geer_graph *g, const QueryCtx &c, const SlotView &s
                              const int32_t *h_ord, int col_tile, int max_hops,
                              std::vector<BatchRec> &recs)
 {
-    const int G = (int)gp.nbat;
-    std::vector<uint64_t> hm(G, 0), host_paths(4 * (size_t)sm.G, 0);
-    std::vector<int64_t> q0s(G);
-    std::vector<int> nbs(G);
-    int levels = 0;
-    for (int k = 0; k < G; ++k) {
-        q0s[k] = gp.p0 + (int64_t)k * gp.B;
-        nbs[k] = (int)std::min<int64_t>(gp.B, gp.pend - q0s[k]);
-        recs[k] = BatchRec();
-        recs[k].q0 = q0s[k];
-        recs[k].nb = nbs[k];
-    }
+    const int nbat = (int)gp.nbat;
+    for (int k = 0; k < nbat; ++k) recs[k] = BatchRec();
+    const SlotArgs sa = slot_args(g, sv, sm, gp);
+    std::vector<uint64_t> hm(nbat, 0);
+    std::vector<const uint64_t *> dmask(nbat, nullptr);
     if (is_static) {
         // level masks from the known depths
         int L = 1;
-        for (int k = 0; k < G; ++k)
-            for (int j = 0; j < nbs[k]; ++j) L = std::max(L, h_target[h_ord[q0s[k] + j]] + 1);
-        levels = L;
-        std::vector<uint64_t> lv((size_t)G * L, 0);
-        for (int k = 0; k < G; ++k)
-            for (int j = 0; j < nbs[k]; ++j) {
-                const int t = h_target[h_ord[q0s[k] + j]];
+        for (int k = 0; k < nbat; ++k)
+            for (int j = 0; j < slot_nb(sa, k); ++j) L = std::max(L, h_target[h_ord[slot_q0(sa, k) + j]] + 1);
+        if ((6 * (size_t)sm.G + (size_t)sm.G * L) * 8 > g->ws.meta.bytes)
+            return fail(GEER_E_DEVICE, "mask words exceed their reservation");
+        std::vector<uint64_t> lv((size_t)nbat * L, 0);
+        for (int k = 0; k < nbat; ++k)
+            for (int j = 0; j < slot_nb(sa, k); ++j) {
+                const int t = h_target[h_ord[slot_q0(sa, k) + j]];
                 for (int h = 1; h <= t && h < L; ++h) lv[(size_t)k * L + h] |= 1ull << j;
             }
-        GEER_TRY(g->ws.meta.reserve(std::max(g->ws.meta.bytes, (6 * (size_t)sm.G + (size_t)G * L) * 8)));
-        SlotMeta sml{g->ws.meta.as<uint64_t>(), sm.G};
-        GEER_HIP(hipMemcpyAsync(sml.level(0, 0, L), lv.data(), lv.size() * 8, hipMemcpyHostToDevice,
-                                c.stream));
-        for (int k = 0; k < G; ++k) {
-            const uint64_t m1 = lv[(size_t)k * L + (L > 1 ? 1 : 0)];
-            if (L < 2 || m1 == 0) continue;
-            GEER_TRY(launch_hop1(g, c, q0s[k], nbs[k], sv.buf(k, 0), sv.bw(k, 0), nullptr, sv.vs, false,
-                                 c.stream));
-            recs[k].hop1 = true;
-            GEER_TRY(launch_epilogue(g, c, q0s[k], nbs[k], 1, sv.buf(k, 0), sv.elem_off(k, 0),
-                                     sml.active(k), sv.vs, 0, c.stream));
-        }
-        for (int h = 2; h < L; ++h)
-            for (int k = 0; k < G; ++k) {
-                const uint64_t mh = lv[(size_t)k * L + h];
-                if (!mh) continue;
-                GEER_TRY(launch_level(g, c, sv, sml, k, q0s[k], nbs[k], h, mh, sml.level(k, h, L),
-                                      sml.active(k), h_s, h_t, h_ord, col_tile, &recs[k], host_paths));
+        if (L < 2) return GEER_OK;
+        GEER_TRY(set_words(sm.level(0, 0, L), lv.data(), lv.size(), c.stream));
+        GEER_TRY(launch_hop1_group(g, c, sa, nbat, false, c.stream));
+        for (int k = 0; k < nbat; ++k) recs[k].hop1 = lv[(size_t)k * L + 1] != 0;
+        GEER_TRY(launch_epilogue_group(g, c, sa, nbat, 1, 0, sv.vs, c.stream));
+        for (int h = 2; h < L; ++h) {
+            bool any = false;
+            for (int k = 0; k < nbat; ++k) {
+                hm[k] = lv[(size_t)k * L + h];
+                dmask[k] = sm.level(k, h, L);
+                any |= hm[k] != 0;
             }
-        (void)levels;
+            if (any)
+                GEER_TRY(run_level(g, c, sv, sm, sa, nbat, h, hm, dmask, h_s, h_t, h_ord, col_tile, recs));
+        }
         return GEER_OK;
     }
     // greedy: level 1 for every batch, then one read of all masks per level
-    for (int k = 0; k < G; ++k) {
-        hipLaunchKernelGGL(k_batch_mask, dim3(1), dim3(64), 0, c.stream, c.qs, q0s[k], nbs[k], sm.active(k));
-        GEER_HIP(hipGetLastError());
-        GEER_TRY(launch_hop1(g, c, q0s[k], nbs[k], sv.buf(k, 0), sv.bw(k, 0), nullptr, sv.vs, false,
-                             c.stream));
+    hipLaunchKernelGGL(k_batch_mask, dim3(nbat), dim3(64), 0, c.stream, c.qs, sa);
+    GEER_HIP(hipGetLastError());
+    GEER_TRY(launch_hop1_group(g, c, sa, nbat, false, c.stream));
+    for (int k = 0; k < nbat; ++k) {
         recs[k].hop1 = true;
-        GEER_TRY(launch_epilogue(g, c, q0s[k], nbs[k], 1, sv.buf(k, 0), sv.elem_off(k, 0), sm.active(k),
-                                 sv.vs, 0, c.stream));
+        dmask[k] = sm.active(k);
     }
+    GEER_TRY(launch_epilogue_group(g, c, sa, nbat, 1, 0, sv.vs, c.stream));
     for (int hop = 2;; ++hop) {
-        GEER_HIP(hipMemcpyAsync(hm.data(), sm.active(0), G * sizeof(uint64_t), hipMemcpyDeviceToHost,
+        GEER_HIP(hipMemcpyAsync(hm.data(), sm.active(0), nbat * sizeof(uint64_t), hipMemcpyDeviceToHost,
                                 c.stream));
         GEER_HIP(hipStreamSynchronize(c.stream));
         bool any = false;
-        for (int k = 0; k < G; ++k) any |= hm[k] != 0;
+        for (int k = 0; k < nbat; ++k) any |= hm[k] != 0;
         if (!any) break;
         if (hop > max_hops)
             return fail(GEER_E_DEVICE, "SMM batch still active after the largest possible l");
-        for (int k = 0; k < G; ++k) {
-            if (!hm[k]) continue;
-            GEER_TRY(launch_level(g, c, sv, sm, k, q0s[k], nbs[k], hop, hm[k], sm.active(k), sm.active(k),
-                                  h_s, h_t, h_ord, col_tile, &recs[k], host_paths));
-        }
+        GEER_TRY(run_level(g, c, sv, sm, sa, nbat, hop, hm, dmask, h_s, h_t, h_ord, col_tile, recs));
     }
     return GEER_OK;
 }
@@ -434,7 +488,7 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
             grp.pool = sv.pool;
             grp.value_size = vs;
             GEER_TRY(amc_phase(g, c, grp, c.stream, p.walk_ilp));
-            for (int k = 0; k < gp.nbat; ++k) GEER_TRY(cleanup_batch(g, c, sv, sm, k, recs[k]));
+            GEER_TRY(cleanup_group(g, c, sv, sm, slot_args(g, sv, sm, gp), (int)gp.nbat, recs));
         }
     }
     return GEER_OK;
@@ -627,14 +681,13 @@ geer_status geer_smm(geer_graph *g, int32_t nq, const int32_t *s, const int32_t 
     GEER_TRY(g->ws.meta.reserve((6 * (size_t)G1 + (size_t)G1 * (hops + 2)) * 8 + 64));
     SlotMeta sm{g->ws.meta.as<uint64_t>(), G1};
     std::vector<BatchRec> recs(1);
-    if (hops > 0) {
-        GroupPlan gp;
-        gp.p0 = 0;
-        gp.nbat = 1;
-        gp.pend = nq;
-        gp.B = nq;
+    GroupPlan gp;
+    gp.p0 = 0;
+    gp.nbat = 1;
+    gp.pend = nq;
+    gp.B = nq;
+    if (hops > 0)
         GEER_TRY(smm_group(g, c, sv, sm, gp, true, target.data(), s, t, ord.data(), tile, hops, recs));
-    }
     GEER_HIP(hipStreamSynchronize(st));
     const size_t n = (size_t)g->n;
     if (hops == 0) {
@@ -692,7 +745,7 @@ geer_status geer_smm(geer_graph *g, int32_t nq, const int32_t *s, const int32_t 
     }
     // restore the sparse buffers to zero
     if (hops > 0) {
-        GEER_TRY(cleanup_batch(g, c, sv, sm, 0, recs[0]));
+        GEER_TRY(cleanup_group(g, c, sv, sm, slot_args(g, sv, sm, gp), 1, recs));
         GEER_HIP(hipStreamSynchronize(st));
     }
     return GEER_OK;

@@ -134,20 +134,23 @@ geer_status launch_init_queries(geer_graph *g, const QueryCtx &c, const int32_t 
 // ----------------------------------------------------------------------------
 
 template <class T>
-__global__ __launch_bounds__(64) void k_hop1(QState qs, int64_t q0,
+__global__ __launch_bounds__(64) void k_hop1(QState qs, SlotArgs sa,
                                              const int32_t *__restrict__ row_ptr,
                                              const int32_t *__restrict__ col_idx,
-                                             const T *__restrict__ inv_deg, T *__restrict__ h1,
-                                             uint32_t *__restrict__ h1_bits, int clear,
-                                             double *__restrict__ cs_m1, double *__restrict__ cs_m2,
-                                             int64_t *__restrict__ cs_sd)
+                                             const T *__restrict__ inv_deg, int clear)
 {
     const int c = blockIdx.x;  // column within the batch
+    const int k = blockIdx.y;  // batch (slot) within the group
     const int j = c >> 1, side = c & 1;
-    const int64_t q = qs.ord[q0 + j];
+    if (j >= slot_nb(sa, k)) return;
+    const int64_t q = qs.ord[slot_q0(sa, k) + j];
     const int lane = threadIdx.x;
     if (!clear && !qs.active_smm[q]) return;
     if (clear && qs.lb[q] < 1) return;  // hop 1 never ran for this pair
+    T *h1 = slot_buf<T>(sa, k, 0);
+    uint32_t *h1_bits = slot_bits(sa, k, 0);
+    double *cs_m1 = slot_cs(sa, k), *cs_m2 = cs_m1 + kCols;
+    int64_t *cs_sd = reinterpret_cast<int64_t *>(cs_m2 + kCols);
     const int32_t u = side ? qs.t[q] : qs.s[q];
     const int32_t b = row_ptr[u], e = row_ptr[u + 1];
     const uint32_t bit = 1u << (c & 31);
@@ -213,17 +216,20 @@ __device__ __forceinline__ void gather_range(const int32_t *__restrict__ col_idx
                 ok[i] = kk < cnt;
                 u[i] = __shfl(myidx, ok[i] ? kk : 0);
             }
-            T2 x[U];
+            // support bits first: a pair whose two bits are clear at u has
+            // exact zeros there, so its values are not fetched (whole lines
+            // of the vector are skipped when none of their pairs reach u)
             uint32_t w[U];
 #pragma unroll
+            for (int i = 0; i < U; ++i) w[i] = ok[i] ? in_bits[(size_t)u[i] * kBitWords + bw] : 0u;
+            T2 x[U];
+#pragma unroll
             for (int i = 0; i < U; ++i) {
-                if (ok[i]) {
+                if ((w[i] >> (col & 31)) & 3u) {
                     x[i] = *reinterpret_cast<const T2 *>(in + (size_t)u[i] * kCols + col);
-                    w[i] = in_bits[(size_t)u[i] * kBitWords + bw];
                 } else {
                     x[i].x = T(0);
                     x[i].y = T(0);
-                    w[i] = 0u;
                 }
             }
 #pragma unroll
@@ -324,7 +330,7 @@ __device__ __forceinline__ void write_block_stats(int lane, int wave, int slot, 
 // the wavefront (the largest degree of its rows), so the index broadcasts
 // always run with every lane active.
 template <class T, int KT>
-__global__ __launch_bounds__(256) void k_hop_light(
+__global__ __launch_bounds__(256, 5) void k_hop_light(
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
     const T *__restrict__ inv_deg, const int32_t *__restrict__ rows, int32_t nrows,
     const T *__restrict__ in, T *__restrict__ out, const uint32_t *__restrict__ in_bits,
@@ -366,17 +372,18 @@ __global__ __launch_bounds__(256) void k_hop_light(
                     ok[i] = k0 + kk + i < d;
                     u[i] = __shfl(myidx, grp * LPR + kk + i);
                 }
-                T2 x[U];
+                // support bits first; clear bits mean exact zeros (not fetched)
                 uint32_t w[U];
 #pragma unroll
+                for (int i = 0; i < U; ++i) w[i] = ok[i] ? in_bits[(size_t)u[i] * kBitWords + bw] : 0u;
+                T2 x[U];
+#pragma unroll
                 for (int i = 0; i < U; ++i) {
-                    if (ok[i]) {
+                    if ((w[i] >> (col & 31)) & 3u) {
                         x[i] = *reinterpret_cast<const T2 *>(in + (size_t)u[i] * kCols + col);
-                        w[i] = in_bits[(size_t)u[i] * kBitWords + bw];
                     } else {
                         x[i].x = T(0);
                         x[i].y = T(0);
-                        w[i] = 0u;
                     }
                 }
 #pragma unroll
@@ -537,6 +544,36 @@ __global__ __launch_bounds__(256) void k_colstat_reduce(const double *__restrict
     }
 }
 
+// Hop-2 column statistics of a group: the kPushSplit partial rows of each
+// column of a pair in the slot's hop-2 mask.  One wavefront per (column, slot).
+__global__ __launch_bounds__(64) void k_colstat_group(SlotArgs sa)
+{
+    const int c = blockIdx.x, k = blockIdx.y, lane = threadIdx.x;
+    if (!((sa.meta[sa.G + k] >> (c >> 1)) & 1ull)) return;
+    const double *hp = slot_hpart(sa, k);
+    const int64_t *hsd = reinterpret_cast<const int64_t *>(hp + 2 * kPushSplit * kCols);
+    double a1 = 0.0, a2 = 0.0;
+    int64_t sd = 0;
+    if (lane < kPushSplit) {
+        const size_t o = (size_t)lane * kCols + c;
+        a1 = hp[o];
+        a2 = hp[kPushSplit * kCols + o];
+        sd = hsd[o];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const double b1 = __shfl_xor(a1, o), b2 = __shfl_xor(a2, o);
+        top2_push(a1, a2, b1);
+        top2_push(a1, a2, b2);
+        sd += __shfl_xor(sd, o);
+    }
+    if (lane == 0) {
+        double *cs = slot_cs(sa, k);
+        cs[c] = a1;
+        cs[kCols + c] = a2;
+        reinterpret_cast<int64_t *>(cs + 2 * kCols)[c] = sd;
+    }
+}
+
 int grid_blocks_dense(const geer_graph *g) { return std::max(1, g->num_cus * 8); }
 
 static int heavy_fin_blocks(const geer_graph *g)
@@ -602,9 +639,9 @@ static geer_status hop_dense_t(geer_graph *g, const HopArgs &a, hipStream_t st)
         GEER_HIP(hipGetLastError());
     } else {
         // keep the partial rows of the (absent) heavy pass neutral
-        GEER_HIP(hipMemsetAsync(p_m1 + (size_t)nb * kCols, 0, (size_t)nf * kCols * sizeof(double), st));
-        GEER_HIP(hipMemsetAsync(p_m2 + (size_t)nb * kCols, 0, (size_t)nf * kCols * sizeof(double), st));
-        GEER_HIP(hipMemsetAsync(p_sd + (size_t)nb * kCols, 0, (size_t)nf * kCols * sizeof(int64_t), st));
+        GEER_TRY(launch_zero(g, p_m1 + (size_t)nb * kCols, (size_t)nf * kCols * sizeof(double), st));
+        GEER_TRY(launch_zero(g, p_m2 + (size_t)nb * kCols, (size_t)nf * kCols * sizeof(double), st));
+        GEER_TRY(launch_zero(g, p_sd + (size_t)nb * kCols, (size_t)nf * kCols * sizeof(int64_t), st));
     }
     return GEER_OK;
 }
@@ -639,7 +676,7 @@ geer_status launch_hop_dense(geer_graph *g, const HopArgs &a, int value_size, hi
         }
         if (s != GEER_OK) return s == GEER_E_INVALID_ARG ? fail(s, "unsupported column tile") : s;
     }
-    double *cs_m1 = ws.colstat.as<double>();
+    double *cs_m1 = a.cs;
     double *cs_m2 = cs_m1 + kCols;
     int64_t *cs_sd = reinterpret_cast<int64_t *>(cs_m2 + kCols);
     double *p_m1 = ws.part.as<double>();
@@ -654,24 +691,18 @@ geer_status launch_hop_dense(geer_graph *g, const HopArgs &a, int value_size, hi
     return GEER_OK;
 }
 
-geer_status launch_hop1(geer_graph *g, const QueryCtx &c, int64_t q0, int nb, void *h1,
-                        uint32_t *h1_bits, const uint64_t *mask, int value_size, bool clear,
-                        hipStream_t st)
+geer_status launch_hop1_group(geer_graph *g, const QueryCtx &c, const SlotArgs &sa, int nslots,
+                              bool clear, hipStream_t st)
 {
-    (void)mask;
-    Workspace &ws = g->ws;
-    double *cs_m1 = ws.colstat.as<double>();
-    double *cs_m2 = cs_m1 + kCols;
-    int64_t *cs_sd = reinterpret_cast<int64_t *>(cs_m2 + kCols);
+    if (nslots <= 0) return GEER_OK;
+    const dim3 grid(2 * sa.B, nslots);
     int tok = prof_begin(g, st);
-    if (value_size == 4)
-        hipLaunchKernelGGL(k_hop1<float>, dim3(2 * nb), dim3(64), 0, st, c.qs, q0, g->d_row_ptr,
-                           g->d_col_idx, g->d_inv_deg_f, (float *)h1, h1_bits, clear ? 1 : 0,
-                           cs_m1, cs_m2, cs_sd);
+    if (g->ws.value_size == 4)
+        hipLaunchKernelGGL(k_hop1<float>, grid, dim3(64), 0, st, c.qs, sa, g->d_row_ptr,
+                           g->d_col_idx, g->d_inv_deg_f, clear ? 1 : 0);
     else
-        hipLaunchKernelGGL(k_hop1<double>, dim3(2 * nb), dim3(64), 0, st, c.qs, q0, g->d_row_ptr,
-                           g->d_col_idx, g->d_inv_deg_d, (double *)h1, h1_bits, clear ? 1 : 0,
-                           cs_m1, cs_m2, cs_sd);
+        hipLaunchKernelGGL(k_hop1<double>, grid, dim3(64), 0, st, c.qs, sa, g->d_row_ptr,
+                           g->d_col_idx, g->d_inv_deg_d, clear ? 1 : 0);
     prof_end(g, tok, PK_HOP1, 0.0, 0.0, st);
     GEER_HIP(hipGetLastError());
     return GEER_OK;
@@ -682,16 +713,20 @@ geer_status launch_hop1(geer_graph *g, const QueryCtx &c, int64_t q0, int nb, vo
 // ----------------------------------------------------------------------------
 
 template <class T>
-__global__ void k_epilogue(QState qs, int64_t q0, int nb, int hop, const T *__restrict__ vec,
-                           int64_t vec_elem_off, const int32_t *__restrict__ row_ptr,
-                           const double *__restrict__ cs_m1, const double *__restrict__ cs_m2,
-                           const int64_t *__restrict__ cs_sd, uint64_t *__restrict__ mask,
-                           int32_t schedule, int32_t tau, double delta)
+__global__ void k_epilogue(QState qs, SlotArgs sa, int hop, int which,
+                           const int32_t *__restrict__ row_ptr, int32_t schedule, int32_t tau,
+                           double delta)
 {
+    const int k = blockIdx.x;  // batch (slot) within the group
     const int j = threadIdx.x;
-    if (j >= nb) return;
-    const int64_t q = qs.ord[q0 + j];
+    if (j >= slot_nb(sa, k)) return;
+    const int64_t q = qs.ord[slot_q0(sa, k) + j];
     if (!qs.active_smm[q]) return;
+    const T *vec = slot_buf<T>(sa, k, which);
+    const int64_t vec_elem_off = slot_elem_off(sa, k, which);
+    const double *cs_m1 = slot_cs(sa, k), *cs_m2 = cs_m1 + kCols;
+    const int64_t *cs_sd = reinterpret_cast<const int64_t *>(cs_m2 + kCols);
+    uint64_t *mask = sa.meta + k;
     const int32_t s = qs.s[q], t = qs.t[q];
     const double ids = 1.0 / (row_ptr[s + 1] - row_ptr[s]);
     const double idt = 1.0 / (row_ptr[t + 1] - row_ptr[t]);
@@ -730,24 +765,17 @@ __global__ void k_epilogue(QState qs, int64_t q0, int nb, int hop, const T *__re
     }
 }
 
-geer_status launch_epilogue(geer_graph *g, const QueryCtx &c, int64_t q0, int nb, int hop,
-                            const void *vec, int64_t vec_elem_off, uint64_t *mask, int value_size,
-                            int dense, hipStream_t st)
+geer_status launch_epilogue_group(geer_graph *g, const QueryCtx &c, const SlotArgs &sa,
+                                  int nslots, int hop, int which, int value_size, hipStream_t st)
 {
-    (void)dense;
-    Workspace &ws = g->ws;
-    double *cs_m1 = ws.colstat.as<double>();
-    double *cs_m2 = cs_m1 + kCols;
-    int64_t *cs_sd = reinterpret_cast<int64_t *>(cs_m2 + kCols);
+    if (nslots <= 0) return GEER_OK;
     int tok = prof_begin(g, st);
     if (value_size == 4)
-        hipLaunchKernelGGL(k_epilogue<float>, dim3(1), dim3(64), 0, st, c.qs, q0, nb, hop,
-                           (const float *)vec, vec_elem_off, g->d_row_ptr, cs_m1, cs_m2, cs_sd,
-                           mask, c.schedule, c.tau, c.delta);
+        hipLaunchKernelGGL(k_epilogue<float>, dim3(nslots), dim3(64), 0, st, c.qs, sa, hop, which,
+                           g->d_row_ptr, c.schedule, c.tau, c.delta);
     else
-        hipLaunchKernelGGL(k_epilogue<double>, dim3(1), dim3(64), 0, st, c.qs, q0, nb, hop,
-                           (const double *)vec, vec_elem_off, g->d_row_ptr, cs_m1, cs_m2, cs_sd,
-                           mask, c.schedule, c.tau, c.delta);
+        hipLaunchKernelGGL(k_epilogue<double>, dim3(nslots), dim3(64), 0, st, c.qs, sa, hop, which,
+                           g->d_row_ptr, c.schedule, c.tau, c.delta);
     prof_end(g, tok, PK_EPILOGUE, 0.0, 0.0, st);
     GEER_HIP(hipGetLastError());
     return GEER_OK;
@@ -817,8 +845,6 @@ namespace geer {
 // in FP64, rounds once to the vector type and records the statistics.
 // ----------------------------------------------------------------------------
 
-constexpr int kPushSplit = 8;  // blocks per column
-
 __device__ __forceinline__ unsigned long long fixed_inv_deg(double inv_d, int shift)
 {
     return __double2ull_rn(ldexp(inv_d, shift));
@@ -833,27 +859,30 @@ constexpr int kPushChunk = 2048;  // neighbours of u staged in LDS per round
 // blocks of the column), so hub rows do not serialise on one wavefront.
 template <class T, int MODE>
 __global__ __launch_bounds__(256) void k_hop2_sparse(
-    QState qs, int64_t q0, const uint64_t *__restrict__ mask_p,
-    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
-    const double *__restrict__ inv_deg_d, unsigned long long *__restrict__ acc, int shift,
-    T *__restrict__ out, uint32_t *__restrict__ out_bits, double *__restrict__ p_m1,
-    double *__restrict__ p_m2, int64_t *__restrict__ p_sd)
+    QState qs, SlotArgs sa, int slot0, const int32_t *__restrict__ row_ptr,
+    const int32_t *__restrict__ col_idx, const double *__restrict__ inv_deg_d,
+    unsigned long long *__restrict__ acc, int shift)
 {
     __shared__ int32_t s_v[kPushChunk];
     __shared__ int32_t s_beg[kPushChunk];
     __shared__ int32_t s_pre[kPushChunk + 1];
     __shared__ int32_t s_tmp[256];
     const int c = blockIdx.x;
-    const int k = blockIdx.y;
+    const int slot = slot0 + (int)blockIdx.y / kPushSplit;
+    const int k = (int)blockIdx.y % kPushSplit;  // this block's share of the column
     const int j = c >> 1;
-    // modes 0/1: per-column path mask (two words); mode 2: the batch's pair mask
+    // modes 0/1: per-column global-path mask (two words); mode 2: the pair mask
+    const uint64_t *mask_p = MODE == 2 ? sa.meta + sa.G + slot : sa.meta + 2 * sa.G + 4 * slot + 2;
     const bool act = MODE == 2 ? (((*mask_p) >> j) & 1ull) : ((mask_p[c >> 6] >> (c & 63)) & 1ull);
+    T *out = slot_buf<T>(sa, slot, 1);
+    uint32_t *out_bits = slot_bits(sa, slot, 1);
+    unsigned long long *acc_s = acc + (size_t)(slot - slot0) * sa.buf_elems;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     T m1 = 0, m2 = 0;
     int64_t sd = 0;
     if (act) {
-        const int64_t q = qs.ord[q0 + j];
+        const int64_t q = qs.ord[slot_q0(sa, slot) + j];
         const int32_t u = (c & 1) ? qs.t[q] : qs.s[q];
         const int32_t b0 = row_ptr[u], du = row_ptr[u + 1] - b0;
         const uint32_t bit = 1u << (c & 31);
@@ -899,9 +928,9 @@ __global__ __launch_bounds__(256) void k_hop2_sparse(
                 const int32_t w = col_idx[s_beg[lo] + (p - s_pre[lo])];
                 const size_t off = (size_t)w * kCols + c;
                 if (MODE == 0) {
-                    atomicAdd(acc + off, fixed_inv_deg(inv_deg_d[v], shift));
+                    atomicAdd(acc_s + off, fixed_inv_deg(inv_deg_d[v], shift));
                 } else if (MODE == 1) {
-                    const unsigned long long tot = atomicExch(acc + off, 0ull);
+                    const unsigned long long tot = atomicExch(acc_s + off, 0ull);
                     if (tot != 0ull) {
                         const T val = (T)(ldexp((double)tot, -shift) * inv_deg_d[w]);
                         out[off] = val;
@@ -942,10 +971,11 @@ __global__ __launch_bounds__(256) void k_hop2_sparse(
             top2_push(a1, a2, s2[w]);
             t += ss[w];
         }
+        double *hp = slot_hpart(sa, slot);
         const size_t o = (size_t)k * kCols + c;
-        p_m1[o] = a1;
-        p_m2[o] = a2;
-        p_sd[o] = t;
+        hp[o] = a1;
+        hp[kPushSplit * kCols + o] = a2;
+        reinterpret_cast<int64_t *>(hp + 2 * kPushSplit * kCols)[o] = t;
     }
 }
 
@@ -957,12 +987,10 @@ __global__ __launch_bounds__(256) void k_hop2_sparse(
 constexpr int kHashCap = 12288;  // 144 KB of the 160 KB LDS
 
 template <class T>
-__global__ __launch_bounds__(512) void k_hop2_lds(
-    QState qs, int64_t q0, const uint64_t *__restrict__ mask_p,
-    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
-    const double *__restrict__ inv_deg_d, int shift, T *__restrict__ out,
-    uint32_t *__restrict__ out_bits, double *__restrict__ p_m1, double *__restrict__ p_m2,
-    int64_t *__restrict__ p_sd)
+__global__ __launch_bounds__(512) void k_hop2_lds(QState qs, SlotArgs sa,
+                                                  const int32_t *__restrict__ row_ptr,
+                                                  const int32_t *__restrict__ col_idx,
+                                                  const double *__restrict__ inv_deg_d, int shift)
 {
     __shared__ int32_t s_key[kHashCap];
     __shared__ unsigned long long s_val[kHashCap];
@@ -973,9 +1001,13 @@ __global__ __launch_bounds__(512) void k_hop2_lds(
     __shared__ double s1[8], s2[8];
     __shared__ int64_t ss[8];
     const int c = blockIdx.x;
+    const int slot = blockIdx.y;
     const int j = c >> 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const bool act = (mask_p[c >> 6] >> (c & 63)) & 1ull;  // per-column path mask
+    const uint64_t *mask_p = sa.meta + 2 * sa.G + 4 * slot;  // per-column LDS-path mask
+    const bool act = (mask_p[c >> 6] >> (c & 63)) & 1ull;
+    T *out = slot_buf<T>(sa, slot, 1);
+    uint32_t *out_bits = slot_bits(sa, slot, 1);
     T m1 = 0, m2 = 0;
     int64_t sd = 0;
     if (act) {
@@ -983,7 +1015,7 @@ __global__ __launch_bounds__(512) void k_hop2_lds(
             s_key[i] = -1;
             s_val[i] = 0ull;
         }
-        const int64_t q = qs.ord[q0 + j];
+        const int64_t q = qs.ord[slot_q0(sa, slot) + j];
         const int32_t u = (c & 1) ? qs.t[q] : qs.s[q];
         const int32_t b0 = row_ptr[u], du = row_ptr[u + 1] - b0;
         __syncthreads();
@@ -1073,56 +1105,45 @@ __global__ __launch_bounds__(512) void k_hop2_lds(
             top2_push(a1, a2, s2[w]);
             t += ss[w];
         }
-        p_m1[c] = a1;  // partial row 0; the global path fills rows 1.. with zeros here
-        p_m2[c] = a2;
-        p_sd[c] = t;
+        // partial row 0 (the other rows of an LDS-path column stay zero)
+        double *hp = slot_hpart(sa, slot);
+        hp[c] = a1;
+        hp[kPushSplit * kCols + c] = a2;
+        reinterpret_cast<int64_t *>(hp + 2 * kPushSplit * kCols)[c] = t;
     }
 }
 
-geer_status launch_hop2_lds(geer_graph *g, const QueryCtx &c, int64_t q0, const uint64_t *mask,
-                            void *out, uint32_t *out_bits, int value_size, hipStream_t st)
+geer_status launch_hop2_lds_group(geer_graph *g, const QueryCtx &c, const SlotArgs &sa,
+                                  int nslots, int value_size, hipStream_t st)
 {
-    Workspace &ws = g->ws;
-    double *p_m1 = ws.part.as<double>();
-    const size_t prows = kPushSplit;
-    double *p_m2 = p_m1 + prows * kCols;
-    int64_t *p_sd = reinterpret_cast<int64_t *>(p_m2 + prows * kCols);
+    if (nslots <= 0) return GEER_OK;
+    const dim3 grid(kCols, nslots);
     int tok = prof_begin(g, st);
     if (value_size == 4)
-        hipLaunchKernelGGL(k_hop2_lds<float>, dim3(kCols), dim3(512), 0, st, c.qs, q0, mask,
-                           g->d_row_ptr, g->d_col_idx, g->d_inv_deg_d, g->fx_shift, (float *)out,
-                           out_bits, p_m1, p_m2, p_sd);
+        hipLaunchKernelGGL(k_hop2_lds<float>, grid, dim3(512), 0, st, c.qs, sa, g->d_row_ptr,
+                           g->d_col_idx, g->d_inv_deg_d, g->fx_shift);
     else
-        hipLaunchKernelGGL(k_hop2_lds<double>, dim3(kCols), dim3(512), 0, st, c.qs, q0, mask,
-                           g->d_row_ptr, g->d_col_idx, g->d_inv_deg_d, g->fx_shift, (double *)out,
-                           out_bits, p_m1, p_m2, p_sd);
+        hipLaunchKernelGGL(k_hop2_lds<double>, grid, dim3(512), 0, st, c.qs, sa, g->d_row_ptr,
+                           g->d_col_idx, g->d_inv_deg_d, g->fx_shift);
     prof_end(g, tok, PK_HOP2_LDS, 0.0, 0.0, st);
     GEER_HIP(hipGetLastError());
     return GEER_OK;
 }
 
-geer_status launch_hop2_sparse(geer_graph *g, const QueryCtx &c, int64_t q0, const uint64_t *mask,
-                               void *out, uint32_t *out_bits, int value_size, int mode,
-                               hipStream_t st)
+geer_status launch_hop2_sparse(geer_graph *g, const QueryCtx &c, const SlotArgs &sa, int slot0,
+                               int nslots, int value_size, int mode, hipStream_t st)
 {
+    if (nslots <= 0) return GEER_OK;
     Workspace &ws = g->ws;
-    GEER_TRY(ws.acc.reserve((size_t)g->n * kCols * sizeof(unsigned long long)));
-    if (!ws.acc_zeroed) {
-        GEER_HIP(hipMemsetAsync(ws.acc.ptr, 0, ws.acc.bytes, st));
-        ws.acc_zeroed = true;
-    }
-    const size_t prows = kPushSplit;
-    GEER_TRY(ws.part.reserve(std::max(ws.part.bytes, prows * kCols * (2 * sizeof(double) + sizeof(int64_t)))));
-    double *p_m1 = ws.part.as<double>();
-    double *p_m2 = p_m1 + prows * kCols;
-    int64_t *p_sd = reinterpret_cast<int64_t *>(p_m2 + prows * kCols);
+    // push and convert use accumulator block (slot - slot0) of each slot
+    if (mode != 2 && nslots > ws.acc_slots)
+        return fail(GEER_E_INVALID_ARG, "hop-2 push covers more slots than accumulators");
     unsigned long long *acc = ws.acc.as<unsigned long long>();
-    const dim3 grid(kCols, kPushSplit);
+    const dim3 grid(kCols, kPushSplit * nslots);
     int tok = prof_begin(g, st);
 #define GEER_PUSH(T_, M_)                                                                      \
-    hipLaunchKernelGGL((k_hop2_sparse<T_, M_>), grid, dim3(256), 0, st, c.qs, q0, mask,         \
-                       g->d_row_ptr, g->d_col_idx, g->d_inv_deg_d, acc, g->fx_shift, (T_ *)out, \
-                       out_bits, p_m1, p_m2, p_sd)
+    hipLaunchKernelGGL((k_hop2_sparse<T_, M_>), grid, dim3(256), 0, st, c.qs, sa, slot0,        \
+                       g->d_row_ptr, g->d_col_idx, g->d_inv_deg_d, acc, g->fx_shift)
     if (value_size == 4) {
         if (mode == 0) GEER_PUSH(float, 0);
         else if (mode == 1) GEER_PUSH(float, 1);
@@ -1138,20 +1159,32 @@ geer_status launch_hop2_sparse(geer_graph *g, const QueryCtx &c, int64_t q0, con
     return GEER_OK;
 }
 
-// Column statistics of the sparse hop: reduce `prows` partial rows.
-geer_status launch_colstat(geer_graph *g, const uint64_t *mask, int prows, hipStream_t st)
+int ensure_hop2_acc(geer_graph *g, int want, hipStream_t st, geer_status *err)
 {
     Workspace &ws = g->ws;
-    double *p_m1 = ws.part.as<double>();
-    double *p_m2 = p_m1 + (size_t)prows * kCols;
-    int64_t *p_sd = reinterpret_cast<int64_t *>(p_m2 + (size_t)prows * kCols);
-    double *cs_m1 = ws.colstat.as<double>();
-    double *cs_m2 = cs_m1 + kCols;
-    int64_t *cs_sd = reinterpret_cast<int64_t *>(cs_m2 + kCols);
-    int t2 = prof_begin(g, st);
-    hipLaunchKernelGGL(k_colstat_reduce, dim3(kCols), dim3(256), 0, st, p_m1, p_m2, p_sd, prows,
-                       mask, cs_m1, cs_m2, cs_sd);
-    prof_end(g, t2, PK_COLSTAT, 0.0, 0.0, st);
+    *err = GEER_OK;
+    if (ws.acc_slots >= want) return ws.acc_slots;
+    // one block of n x kCols 64-bit accumulators per slot, within a quarter
+    // of the free device memory (at least one block)
+    const size_t per = (size_t)g->n * kCols * sizeof(unsigned long long);
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
+    const size_t fit = (free_b + ws.acc.bytes) / 4 / per;
+    const int slots = (int)std::max<size_t>(1, std::min<size_t>((size_t)want, fit));
+    if (slots <= ws.acc_slots) return ws.acc_slots;
+    ws.acc_slots = 0;  // reserve() releases the old blocks
+    if ((*err = ws.acc.reserve((size_t)slots * per)) != GEER_OK) return 0;
+    if ((*err = launch_zero(g, ws.acc.ptr, (size_t)slots * per, st)) != GEER_OK) return 0;
+    ws.acc_slots = slots;
+    return slots;
+}
+
+geer_status launch_colstat_group(geer_graph *g, const SlotArgs &sa, int nslots, hipStream_t st)
+{
+    if (nslots <= 0) return GEER_OK;
+    int tok = prof_begin(g, st);
+    hipLaunchKernelGGL(k_colstat_group, dim3(kCols, nslots), dim3(64), 0, st, sa);
+    prof_end(g, tok, PK_COLSTAT, 0.0, 0.0, st);
     GEER_HIP(hipGetLastError());
     return GEER_OK;
 }
