@@ -62,6 +62,8 @@ def roofline_of(prof: dict, steps: int) -> tuple[dict, dict]:
         if r["alg_bytes"] > 0 and r["total_ms"] > 0:
             entry["achieved_GBs"] = r["alg_bytes"] / (r["total_ms"] * 1e-3) / 1e9
             entry["alg_bytes_per_launch"] = r["alg_bytes"] / r["launches"]
+        if r["work_units"] > 0:
+            entry["units_per_launch"] = r["work_units"] / r["launches"]
         table[name] = entry
     cands = [n for n in table if "achieved_GBs" in table[n]]
     dom = max(cands, key=lambda n: table[n]["ms_per_step"])

@@ -34,7 +34,6 @@ __device__ __forceinline__ bool one_hop_from_graph(int32_t lb, int32_t ds, int32
 __global__ __launch_bounds__(1024) void k_amc_plan(QState qs, int64_t q0, int nq, int round,
                                                    int64_t *__restrict__ chunk_off,
                                                    int64_t *__restrict__ total,
-                                                   int32_t *__restrict__ overflow,
                                                    int64_t *__restrict__ steps,
                                                    const int32_t *__restrict__ row_ptr)
 {
@@ -50,7 +49,6 @@ __global__ __launch_bounds__(1024) void k_amc_plan(QState qs, int64_t q0, int nq
         int64_t q = qs.ord[q0 + i];
         if (qs.active_amc[q]) {
             int64_t eta = qs.eta1[q] << round;
-            if (eta >= (int64_t(1) << 32)) *overflow = 1;
             local += (eta + kPairsPerChunk - 1) / kPairsPerChunk;
             const unsigned long long st = (unsigned long long)(2 * eta * qs.lf[q]);
             atomicAdd(&s_steps, st);
@@ -83,6 +81,48 @@ __global__ __launch_bounds__(1024) void k_amc_plan(QState qs, int64_t q0, int nq
         *total = s_sum[1023];
         steps[0] = (int64_t)s_steps;
         steps[1] = (int64_t)s_vsteps;
+    }
+}
+
+// Upper bound of the chunks of any batch of a group: every pair's largest
+// batch is its last (eta_1 2^(tau_q - 1)), so the sum of those chunk counts
+// bounds every round's total.  out: [0] the bound, [1] overflow flag (a batch
+// of 2^32 walk pairs or more), [2] the largest per-pair batch count.
+__global__ __launch_bounds__(1024) void k_amc_bound(QState qs, int64_t q0, int nq,
+                                                    int64_t *__restrict__ out)
+{
+    __shared__ unsigned long long s_chunks;
+    __shared__ int s_over, s_tau;
+    if (threadIdx.x == 0) {
+        s_chunks = 0;
+        s_over = 0;
+        s_tau = 0;
+    }
+    __syncthreads();
+    unsigned long long chunks = 0;
+    int over = 0, tmax = 0;
+    for (int i = threadIdx.x; i < nq; i += blockDim.x) {
+        const int64_t q = qs.ord[q0 + i];
+        if (!qs.active_amc[q]) continue;
+        const int tq = qs.tau_q[q];
+        const int64_t e1 = qs.eta1[q];
+        // eta_1 2^(tq - 1) >= 2^32  <=>  eta_1 >= 2^(33 - tq)
+        if (tq > 33 || e1 >= (int64_t(1) << (33 - tq))) {
+            over = 1;
+            continue;
+        }
+        const int64_t eta = e1 << (tq - 1);
+        chunks += (unsigned long long)((eta + kPairsPerChunk - 1) / kPairsPerChunk);
+        tmax = max(tmax, tq);
+    }
+    atomicAdd(&s_chunks, chunks);
+    if (over) atomicOr(&s_over, 1);
+    atomicMax(&s_tau, tmax);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = (int64_t)s_chunks;
+        out[1] = s_over;
+        out[2] = s_tau;
     }
 }
 
@@ -286,29 +326,35 @@ geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hip
     GEER_TRY(ws.chunk_off.reserve(((size_t)nq + 1) * sizeof(int64_t)));
     int64_t *chunk_off = ws.chunk_off.as<int64_t>();
     int64_t *d_total = ws.misc.as<int64_t>() + 8;
-    int32_t *d_over = reinterpret_cast<int32_t *>(ws.misc.as<int64_t>() + 9);
-    int64_t *d_steps = ws.misc.as<int64_t>() + 10;
-    GEER_HIP(hipMemsetAsync(d_over, 0, sizeof(int32_t), st));
+    int64_t *d_bound = ws.misc.as<int64_t>() + 12;
+    // one host read per group: the chunk bound sizes the partials and the
+    // grid, and the rounds then run without host synchronisation (rounds in
+    // which no pair is left launch empty grids)
+    hipLaunchKernelGGL(k_amc_bound, dim3(1), dim3(1024), 0, st, c.qs, grp.q0, nq, d_bound);
+    GEER_HIP(hipGetLastError());
+    int64_t host[3] = {0, 0, 0};
+    GEER_HIP(hipMemcpyAsync(host, d_bound, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    GEER_HIP(hipStreamSynchronize(st));
+    if (host[1] != 0) return fail(GEER_E_INVALID_ARG, "AMC batch exceeds 2^32 walk pairs for a query");
+    const int64_t bound = host[0];
+    const int rounds = (int)std::min<int64_t>(host[2], c.tau);
+    if (bound == 0 || rounds <= 0) return GEER_OK;
+    GEER_TRY(ws.zpart.reserve((size_t)bound * sizeof(double2)));
+    const int blocks = (int)std::min<int64_t>((bound + 3) / 4, (int64_t)g->num_cus * 16);
     const uint32_t key0 = (uint32_t)c.seed, key1 = (uint32_t)(c.seed >> 32);
-    for (int round = 0; round < c.tau; ++round) {
+    const void *rec = g->d_walk_rec;
+    const uint32_t sb = (uint32_t)g->rec_sb, sd = (uint32_t)g->rec_sd;
+    auto *zp = ws.zpart.as<double2>();
+    for (int round = 0; round < rounds; ++round) {
+        // walk steps of the batch (all, and those reading SMM vectors) for the
+        // profiler's byte count, else into scratch
+        int counter = -1;
+        int64_t *d_steps = prof_counter(g, &counter);
+        if (!d_steps) d_steps = ws.misc.as<int64_t>() + 10;
         hipLaunchKernelGGL(k_amc_plan, dim3(1), dim3(1024), 0, st, c.qs, grp.q0, nq, round,
-                           chunk_off, d_total, d_over, d_steps, g->d_row_ptr);
+                           chunk_off, d_total, d_steps, g->d_row_ptr);
         GEER_HIP(hipGetLastError());
-        int64_t host[4] = {0, 0, 0, 0};
-        GEER_HIP(hipMemcpyAsync(host, d_total, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        GEER_HIP(hipStreamSynchronize(st));
-        if (((int32_t *)&host[1])[0] != 0)
-            return fail(GEER_E_INVALID_ARG, "AMC batch exceeds 2^32 walk pairs for a query");
-        const int64_t total = host[0];
-        if (total == 0) break;
-        GEER_TRY(ws.zpart.reserve((size_t)total * sizeof(double2)));
-        const int64_t want_blocks = (total + 3) / 4;
-        const int blocks = (int)std::min<int64_t>(want_blocks, (int64_t)g->num_cus * 16);
-        const double steps = (double)host[2], vsteps = (double)host[3];
         int tok = prof_begin(g, st);
-        const void *rec = g->d_walk_rec;
-        const uint32_t sb = (uint32_t)g->rec_sb, sd = (uint32_t)g->rec_sd;
-        auto *zp = ws.zpart.as<double2>();
 #define GEER_WALK_LAUNCH(T, RB)                                                                 \
     hipLaunchKernelGGL((k_walk<T, RB>), dim3(blocks), dim3(256), 0, st, c.qs, grp.q0, nq, round, \
                        chunk_off, d_total, g->d_row_ptr, g->d_col_idx, rec, sb, sd,             \
@@ -321,13 +367,13 @@ geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hip
             else GEER_WALK_LAUNCH(double, 16);
         }
 #undef GEER_WALK_LAUNCH
+        GEER_HIP(hipGetLastError());
         // per step: one walk record; steps of pairs whose vectors are read
         // also fetch the pair's two values at the new node
-        prof_end(g, tok, PK_WALK, (double)g->walk_rec_bytes * steps + 2.0 * grp.value_size * vsteps,
-                 steps, st);
-        GEER_HIP(hipGetLastError());
+        prof_end_counted(g, tok, PK_WALK, counter, (double)g->walk_rec_bytes,
+                         2.0 * grp.value_size, st);
         hipLaunchKernelGGL(k_amc_stop, dim3((nq + 3) / 4), dim3(256), 0, st, c.qs, grp.q0, nq,
-                           round, chunk_off, ws.zpart.as<double2>(), c.tau, c.delta);
+                           round, chunk_off, zp, c.tau, c.delta);
         GEER_HIP(hipGetLastError());
     }
     return GEER_OK;

@@ -112,10 +112,18 @@ struct ProfRec {
     int kind;
     hipEvent_t a, b;
     double bytes, units;
+    // counted records: bytes = per_unit * c0 + per_unit2 * c1 and units = c0,
+    // with (c0, c1) written on the device into counter slot `counter`
+    int counter = -1;
+    double per_unit = 0.0, per_unit2 = 0.0;
 };
+
+constexpr int kProfCounters = 4096;  // device counter pairs between two flushes
 
 struct Profiler {
     bool on = false;
+    int64_t *d_counters = nullptr;  // kProfCounters x 2 int64
+    int n_counters = 0;
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> spare;
     int64_t launches[PK_COUNT] = {};
@@ -364,6 +372,11 @@ geer_status launch_walk_traces(geer_graph *g, int32_t nw, const int32_t *start, 
 int prof_begin(geer_graph *g, hipStream_t st);
 void prof_end(geer_graph *g, int token, int kind, double bytes, double units, hipStream_t st);
 void prof_add_units(geer_graph *g, int kind, double units);
+// A device slot of two int64 counters for a counted record, or nullptr when
+// profiling is off (kernels then write their counts to scratch).
+int64_t *prof_counter(geer_graph *g, int *index);
+void prof_end_counted(geer_graph *g, int token, int kind, int counter, double per_unit,
+                      double per_unit2, hipStream_t st);
 
 geer_status launch_learned(geer_graph *g, const QueryCtx &c, const geer_model *m, float *d_feat,
                            int32_t tau_max, hipStream_t st);

@@ -85,10 +85,18 @@ void prof_add_units(geer_graph *g, int kind, double units)
 static geer_status prof_flush(geer_graph *g)
 {
     Profiler &p = g->prof;
+    for (ProfRec &r : p.recs) GEER_HIP(hipEventSynchronize(r.b));
+    std::vector<int64_t> cnt(2 * (size_t)p.n_counters);
+    if (p.n_counters > 0)
+        GEER_HIP(hipMemcpy(cnt.data(), p.d_counters, cnt.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
     for (ProfRec &r : p.recs) {
-        GEER_HIP(hipEventSynchronize(r.b));
         float ms = 0.f;
         GEER_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        if (r.counter >= 0) {
+            const double c0 = (double)cnt[2 * (size_t)r.counter], c1 = (double)cnt[2 * (size_t)r.counter + 1];
+            r.bytes = r.per_unit * c0 + r.per_unit2 * c1;
+            r.units = c0;
+        }
         p.launches[r.kind] += 1;
         p.ms[r.kind] += ms;
         p.bytes[r.kind] += r.bytes;
@@ -97,7 +105,38 @@ static geer_status prof_flush(geer_graph *g)
         p.spare.push_back(r.b);
     }
     p.recs.clear();
+    p.n_counters = 0;
     return GEER_OK;
+}
+
+int64_t *prof_counter(geer_graph *g, int *index)
+{
+    Profiler &p = g->prof;
+    *index = -1;
+    if (!p.on) return nullptr;
+    if (!p.d_counters) {
+        if (hipMalloc(&p.d_counters, (size_t)kProfCounters * 2 * sizeof(int64_t)) != hipSuccess) {
+            p.d_counters = nullptr;
+            return nullptr;
+        }
+    }
+    if (p.n_counters == kProfCounters && prof_flush(g) != GEER_OK) return nullptr;
+    *index = p.n_counters++;
+    return p.d_counters + 2 * (size_t)*index;
+}
+
+void prof_end_counted(geer_graph *g, int token, int kind, int counter, double per_unit,
+                      double per_unit2, hipStream_t st)
+{
+    Profiler &p = g->prof;
+    if (!p.on || token < 0 || token >= (int)p.recs.size()) return;
+    ProfRec &r = p.recs[token];
+    r.kind = kind;
+    r.bytes = r.units = 0.0;
+    r.counter = counter;
+    r.per_unit = per_unit;
+    r.per_unit2 = per_unit2;
+    (void)hipEventRecord(r.b, st);
 }
 
 }  // namespace geer
@@ -333,6 +372,7 @@ void geer_graph_destroy(geer_graph *g)
         (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t e : g->prof.spare) (void)hipEventDestroy(e);
+    if (g->prof.d_counters) (void)hipFree(g->prof.d_counters);
     if (g->stream) (void)hipStreamDestroy(g->stream);
     delete g;
 }

@@ -8,9 +8,9 @@
 
 namespace geer {
 
-// misc scratch layout (int64 words): [0] active mask of the current batch,
-// [8] AMC chunk total, [9] AMC overflow flag, [10] walk steps of the AMC
-// batch, [11] those of its steps that read SMM vectors
+// misc scratch layout (int64 words): [8] AMC chunk total of the current
+// round, [10, 12) walk steps of the round (when not profiled), [12, 15) AMC
+// chunk bound, overflow flag and largest batch count of the group
 static constexpr int kMiscWords = 16;
 
 geer_status ensure_qstate(geer_graph *g, int64_t nq, QState *qs)

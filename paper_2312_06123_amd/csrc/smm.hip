@@ -330,7 +330,7 @@ __device__ __forceinline__ void write_block_stats(int lane, int wave, int slot, 
 // the wavefront (the largest degree of its rows), so the index broadcasts
 // always run with every lane active.
 template <class T, int KT>
-__global__ __launch_bounds__(256, 5) void k_hop_light(
+__global__ __launch_bounds__(256, (KT == 128 && sizeof(T) == 4) ? 8 : 5) void k_hop_light(
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
     const T *__restrict__ inv_deg, const int32_t *__restrict__ rows, int32_t nrows,
     const T *__restrict__ in, T *__restrict__ out, const uint32_t *__restrict__ in_bits,
