@@ -138,7 +138,7 @@ template <> struct WalkRec<8> {
     static __device__ __forceinline__ void load(const void *rec, int64_t e, uint32_t sb,
                                                 uint32_t sd, int32_t &v, int32_t &b, int32_t &d)
     {
-        const uint64_t x = static_cast<const uint64_t *>(rec)[e];
+        const uint64_t x = __builtin_nontemporal_load(static_cast<const uint64_t *>(rec) + e);
         v = (int32_t)(x & ((1ull << sb) - 1));
         b = (int32_t)((x >> sb) & ((1ull << (sd - sb)) - 1));
         d = (int32_t)(x >> sd);
@@ -167,6 +167,7 @@ __device__ __forceinline__ bool lds_row_contains(const int32_t *row, int32_t x)
 
 // Groups up to this many pairs keep their chunk offsets in LDS.
 constexpr int kChunkOffLds = 1024;
+constexpr int kXcds = 8;  // accelerator complex dies of an MI355X
 
 template <class T, int RB>
 __global__ __launch_bounds__(256) void k_walk(QState qs, int64_t q0, int nq, int round,
@@ -190,11 +191,17 @@ __global__ __launch_bounds__(256) void k_walk(QState qs, int64_t q0, int nq, int
     const int64_t *off = lds_off ? s_off : chunk_off;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int64_t gw = (int64_t)blockIdx.x * 4 + wv;
-    const int64_t nw = (int64_t)gridDim.x * 4;
     const int64_t total = *total_p;
+    // Blocks are dealt to the 8 XCDs round-robin; XCD x takes the x-th eighth
+    // of the chunks (chunks are ordered by batch slot), so the vector rows its
+    // walks revisit belong to few slots and can stay in that XCD's L2.
+    const int nx = gridDim.x % kXcds == 0 ? kXcds : 1;
+    const int xcd = blockIdx.x % nx;
+    const int64_t c_lo = total * xcd / nx, c_hi = total * (xcd + 1) / nx;
+    const int64_t gw = (int64_t)(blockIdx.x / nx) * 4 + wv;
+    const int64_t nw = (int64_t)(gridDim.x / nx) * 4;
     const uint32_t side = lane & 1;
-    for (int64_t c = gw; c < total; c += nw) {
+    for (int64_t c = c_lo + gw; c < c_hi; c += nw) {
         // pair of this chunk: largest i with off[i] <= c
         int lo = 0, hi = nq;
         while (hi - lo > 1) {
@@ -340,7 +347,8 @@ geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hip
     const int rounds = (int)std::min<int64_t>(host[2], c.tau);
     if (bound == 0 || rounds <= 0) return GEER_OK;
     GEER_TRY(ws.zpart.reserve((size_t)bound * sizeof(double2)));
-    const int blocks = (int)std::min<int64_t>((bound + 3) / 4, (int64_t)g->num_cus * 16);
+    int blocks = (int)std::min<int64_t>((bound + 3) / 4, (int64_t)g->num_cus * 16);
+    if (blocks >= kXcds) blocks -= blocks % kXcds;  // whole rounds over the XCDs
     const uint32_t key0 = (uint32_t)c.seed, key1 = (uint32_t)(c.seed >> 32);
     const void *rec = g->d_walk_rec;
     const uint32_t sb = (uint32_t)g->rec_sb, sd = (uint32_t)g->rec_sd;
