@@ -25,6 +25,8 @@ from __future__ import annotations
 
 import dataclasses
 
+import os
+
 import numpy as np
 
 __all__ = [
@@ -96,19 +98,23 @@ def from_edges(n: int, edges: np.ndarray, *, largest_component: bool = False,
     key = np.unique(lo * n + hi)
     lo = key // n
     hi = key % n
-    src = np.concatenate([lo, hi])
-    dst = np.concatenate([hi, lo])
+    # both directions, sorted by (row, column) through one key sort
+    key = np.concatenate([lo * n + hi, hi * n + lo])
+    del lo, hi
+    key.sort()
+    src = key // n
+    dst = key % n
+    del key
     if largest_component:
         keep_nodes = _largest_component(n, src, dst)
-        relabel = np.full(n, -1, dtype=np.int64)
-        relabel[keep_nodes] = np.arange(keep_nodes.size, dtype=np.int64)
-        ok = relabel[src] >= 0
-        src = relabel[src[ok]]
-        dst = relabel[dst[ok]]
-        n = int(keep_nodes.size)
-    order = np.lexsort((dst, src))
-    src = src[order]
-    dst = dst[order]
+        if keep_nodes.size < n:
+            relabel = np.full(n, -1, dtype=np.int64)
+            relabel[keep_nodes] = np.arange(keep_nodes.size, dtype=np.int64)
+            ok = relabel[src] >= 0
+            # the relabelling is increasing, so the (row, column) order survives
+            src = relabel[src[ok]]
+            dst = relabel[dst[ok]]
+            n = int(keep_nodes.size)
     counts = np.bincount(src, minlength=n)
     row_ptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=row_ptr[1:])
@@ -119,7 +125,10 @@ def _largest_component(n: int, src: np.ndarray, dst: np.ndarray) -> np.ndarray:
     import scipy.sparse as sp
     from scipy.sparse.csgraph import connected_components
 
-    adj = sp.csr_matrix((np.ones(src.size, dtype=np.int8), (src, dst)), shape=(n, n))
+    # (src, dst) arrive sorted by row, so the CSR is built directly
+    indptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(src, minlength=n), out=indptr[1:])
+    adj = sp.csr_matrix((np.ones(src.size, dtype=np.int8), dst, indptr), shape=(n, n))
     ncomp, labels = connected_components(adj, directed=False)
     sizes = np.bincount(labels, minlength=ncomp)
     # nodes of degree 0 form singleton components; never pick one of those
@@ -202,35 +211,42 @@ def rmat(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int) 
     """R-MAT graph with 2^scale nodes and edge_factor * 2^scale edge samples.
 
     Each sample descends ``scale`` levels of the adjacency matrix, choosing a
-    quadrant with probabilities (a, b, c, 1 - a - b - c).  Node labels are then
-    permuted by a seeded permutation (removing the generator's id locality),
-    the result is symmetrised and deduplicated, and the largest component
-    is kept.
+    quadrant with probabilities (a, b, c, 1 - a - b - c) from one uniform draw
+    per level.  Samples come in chunks of 2^22, each with its own child of the
+    seed's SeedSequence (so chunks can be drawn in parallel and the result does
+    not depend on the thread count).  Node labels are then permuted by a seeded
+    permutation (removing the generator's id locality), the result is
+    symmetrised and deduplicated, and the largest component is kept.
     """
-    rng = np.random.default_rng(seed)
+    from concurrent.futures import ThreadPoolExecutor
+
     n = 1 << scale
     m_samples = edge_factor * n
-    ab = a + b
-    a_norm = a / ab
-    c_norm = c / (1.0 - ab)
-    perm = rng.permutation(n).astype(np.int64)
+    chunk = 1 << 22
+    nchunks = (m_samples + chunk - 1) // chunk
+    seqs = np.random.SeedSequence(seed).spawn(nchunks + 1)
+    perm = np.random.default_rng(seqs[0]).permutation(n).astype(np.int64)
+    t1, t2, t3 = np.float32(a), np.float32(a + b), np.float32(a + b + c)
     out = np.empty((m_samples, 2), dtype=np.int64)
-    chunk = 1 << 23
-    for lo in range(0, m_samples, chunk):
-        hi = min(m_samples, lo + chunk)
-        cnt = hi - lo
+
+    def draw(i):
+        lo = i * chunk
+        cnt = min(m_samples, lo + chunk) - lo
+        rng = np.random.default_rng(seqs[i + 1])
         src = np.zeros(cnt, dtype=np.int64)
         dst = np.zeros(cnt, dtype=np.int64)
         for level in range(scale):
-            bit = np.int64(1) << (scale - 1 - level)
-            r1 = rng.random(cnt)
-            r2 = rng.random(cnt)
-            row_hi = r1 >= ab
-            col_hi = np.where(row_hi, r2 >= c_norm, r2 >= a_norm)
-            src |= np.where(row_hi, bit, 0)
-            dst |= np.where(col_hi, bit, 0)
-        out[lo:hi, 0] = perm[src]
-        out[lo:hi, 1] = perm[dst]
+            u = rng.random(cnt, dtype=np.float32)
+            # quadrant 0..3 = (row bit, column bit) with probabilities a, b, c, d
+            q = (u >= t1).astype(np.int64) + (u >= t2) + (u >= t3)
+            shift = scale - 1 - level
+            src |= (q >> 1) << shift
+            dst |= (q & 1) << shift
+        out[lo:lo + cnt, 0] = perm[src]
+        out[lo:lo + cnt, 1] = perm[dst]
+
+    with ThreadPoolExecutor(max_workers=max(1, min(8, os.cpu_count() or 1))) as ex:
+        list(ex.map(draw, range(nchunks)))
     return from_edges(n, out, largest_component=True,
                       name=f"rmat(scale={scale},ef={edge_factor},seed={seed})")
 

@@ -53,6 +53,7 @@ def sweep(gg, s, t, eps, seed=7):
             p = G.geer_params_default(seed=seed, tau=tau)
             r, st = G.geer_query(gg.handle, s, t, eps, p, stats=True, fixed_ell_b=lb)
             out[(lb, tau)] = (r, st)
+            log(f"  schedule l_b={lb} tau={tau}: {len(s)} pairs")
     return out
 
 
@@ -96,17 +97,35 @@ def label(feats, runs, r_ref, rng, n_rho=4):
     return np.concatenate(Xs), np.concatenate(Ys), np.concatenate(Ws)
 
 
-def graph_runs(g, nq, eps, seed, rng):
-    """Features, schedule sweep and reference answers on one training graph."""
+def graph_runs(g, nq, eps_choices, seed, rng):
+    """Features, schedule sweep and reference answers on one training graph.
+    Each pair draws its eps from ``eps_choices``."""
     s, t = I.uniform_pairs(g.n, nq, seed)
+    eps = np.random.default_rng(seed + 1).choice(np.asarray(eps_choices, dtype=np.float64), nq)
     with G.Graph(g.n, g.row_ptr32(), g.col_idx) as gg:
         lam = G.geer_graph_compute_lambda(gg.handle, 300, 1e-9, seed)
         t0 = time.time()
         runs = sweep(gg, s, t, eps, seed)
         log(f"{g.name}: {len(runs) * nq} GEER runs in {time.time() - t0:.1f} s (lambda={lam:.4f})")
         r_ref = reference(gg, s, t)
+        log(f"  reference answers (SMM only, eps {EPS_REF})")
         feats = G.geer_features(gg.handle, s, t, eps)
     return label(feats, runs, r_ref, rng)
+
+
+# Training graphs: (generator, pairs, eps choices, pair seed).  The config-1
+# uniform graph alone has no degree skew and short walks; the power-law and
+# R-MAT graphs widen the features the model sees (hub-dominated neighbour
+# sums, lambda from 0.6 to 0.9, so l from a few hops to ~70).
+def training_graphs(scale=1.0):
+    def q(n):
+        return max(16, int(n * scale))
+    return [
+        (lambda: I.erdos_renyi_path(10_000, 10, 1001), q(4000), (0.05,), 4001),
+        (lambda: I.chung_lu(200_000, 2.1, 20, 5004), q(3000), (0.02, 0.05, 0.1), 4002),
+        (lambda: I.chung_lu(300_000, 2.1, 12, 5005), q(3000), (0.02, 0.05, 0.1), 4003),
+        (lambda: I.rmat(17, 16, 0.57, 0.19, 0.19, 5006), q(2500), (0.02, 0.05, 0.1), 4004),
+    ]
 
 
 def train_model(X, Y, W, steps=30000, seed=11, lr=2e-3):
@@ -124,27 +143,20 @@ def train_model(X, Y, W, steps=30000, seed=11, lr=2e-3):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
-    ap.add_argument("--er-queries", type=int, default=6000)
-    ap.add_argument("--cl-queries", type=int, default=6500)
-    ap.add_argument("--cl-nodes", type=int, default=200_000)
-    ap.add_argument("--eps", type=float, default=0.05)
+    ap.add_argument("--scale", type=float, default=1.0, help="multiplies every graph's pair count")
     ap.add_argument("--steps", type=int, default=30000)
     ap.add_argument("--report", default=None)
     a = ap.parse_args(argv)
     rng = np.random.default_rng(4)
     parts = []
-    # the small uniform-random graph of the correctness configuration
-    g1 = I.erdos_renyi_path(10_000, 10, 1001)
-    parts.append(graph_runs(g1, a.er_queries, a.eps, 4001, rng))
-    # a small power-law graph: the uniform graph has no degree skew, so its
-    # features cannot cover the hub-dominated graphs the model is used on
-    if a.cl_queries > 0:
-        g2 = I.chung_lu(a.cl_nodes, 2.1, 20, 5004)
-        parts.append(graph_runs(g2, a.cl_queries, a.eps, 4002, rng))
+    runs_total = 0
+    for make, nq, eps_choices, seed in training_graphs(a.scale):
+        g = make()
+        parts.append(graph_runs(g, nq, eps_choices, seed, rng))
+        runs_total += nq * len(DEPTHS) * len(TAUS)
     X = np.concatenate([p[0] for p in parts])
     Y = np.concatenate([p[1] for p in parts])
     W = np.concatenate([p[2] for p in parts])
-    runs_total = (a.er_queries + a.cl_queries) * len(DEPTHS) * len(TAUS)
     log(f"{X.shape[0]} labelled samples from {runs_total} GEER runs")
     t0 = time.time()
     m, losses, _ = train_model(X, Y, W, a.steps)
@@ -156,6 +168,7 @@ def main(argv=None):
             json.dump({"samples": int(X.shape[0]), "runs": runs_total,
                        "loss_first": float(losses[:200].mean()),
                        "loss_last": float(losses[-200:].mean()),
+                       "feature_min": X.min(axis=0).tolist(), "feature_max": X.max(axis=0).tolist(),
                        "label_lb_hist": np.bincount(Y[:, 0].astype(int)).tolist(),
                        "label_tau_hist": np.bincount(Y[:, 1].astype(int)).tolist()}, f)
     return 0

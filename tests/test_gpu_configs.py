@@ -1,0 +1,142 @@
+"""Parity at the shapes of the other workloads (each a module of its own).
+
+  * ER n = 10^4, mean degree 10, 1,000 uniform pairs, eps = 0.1, FP64 vectors
+    and sums: every pair replayed by the FP64 checker with the same walks;
+    decisions agree on >= 99% of pairs and the answers there to 1e-9;
+  * R-MAT scale 22 (a = 0.57, b = c = 0.19), 100,000 pairs (half uniform,
+    half degree-proportional), per-pair eps drawn from {0.02, 0.05, 0.1},
+    autotuned tile: stratified sample checked against the exact resistance
+    (|r' - r| <= eps) and replayed by the checker; the graph's bit widths
+    exceed 64, so the walks run on 16-byte records;
+  * the learned checkpoint on a fresh Chung-Lu graph (n = 2 * 10^6, the 1M
+    configuration's parameters), 50,000 uniform pairs, eps = 0.05: the model
+    applies to most pairs, sampled answers are within eps of the exact
+    resistance and equal the checker's run at the same (l_b, tau).
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2312_06123_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+G = pytest.importorskip("paper_2312_06123_amd.geer")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _agree(st, sto):
+    return ((st["ell"] == sto["ell"]) & (st["ell_b"] == sto["ell_b"]) &
+            (st["eta1"] == sto["eta1"]) & (st["batches_run"] == sto["batches_run"]))
+
+
+# ---------------------------------------------------------------------------
+# ER n = 10^4, FP64 throughout
+# ---------------------------------------------------------------------------
+
+def test_er10k_fp64_every_pair_replayed():
+    g = I.erdos_renyi_path(10_000, 10, 1001)
+    assert g.nnz == 100_000
+    s, t = I.uniform_pairs(g.n, 1000, 2001)
+    with G.Graph(g.n, g.row_ptr32(), g.col_idx) as gg:
+        lam = G.geer_graph_compute_lambda(gg.handle, 300, 1e-10, 7)
+        p = G.geer_params_default(seed=3001, flags=G.GEER_FLAG_FP64_VECTORS)
+        r, st = G.geer_query(gg.handle, s, t, 0.1, p, stats=True)
+    ref = oracle.lambda_arpack(g.row_ptr, g.col_idx, tol=1e-12)
+    assert ref - 1e-9 <= lam <= ref + 1e-6
+    ro, sto = oracle.geer(g.row_ptr, g.col_idx, s, t, 0.1, lam, seed=3001)
+    assert np.array_equal(st["ell"], sto["ell"])
+    agree = _agree(st, sto)
+    assert agree.mean() >= 0.99
+    assert np.all(np.abs(r[agree] - ro[agree]) <= 1e-9 * np.maximum(1.0, np.abs(ro[agree])))
+    ex, _ = oracle.exact_cg(g.row_ptr, g.col_idx, s, t, tol=1e-12)
+    assert np.mean(np.abs(r - ex) <= 0.1) >= 0.99
+
+
+# ---------------------------------------------------------------------------
+# R-MAT scale 22, mixed eps, uniform + degree-proportional pairs
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def rmat22_run():
+    g = I.rmat(22, 16, 0.57, 0.19, 0.19, 1003)
+    nq = 100_000
+    su, tu = I.uniform_pairs(g.n, nq // 2, 2003)
+    sd, td = I.degree_pairs(g, nq // 2, 2103)
+    s = np.concatenate([su, sd])
+    t = np.concatenate([tu, td])
+    eps = np.random.default_rng(2203).choice(np.array([0.02, 0.05, 0.1]), nq)
+    with G.Graph(g.n, g.row_ptr32(), g.col_idx) as gg:
+        lam = G.geer_graph_compute_lambda(gg.handle, 400, 1e-8, 7)
+        ts, tt = I.uniform_pairs(g.n, 1024, 2303)
+        G.geer_autotune(gg.handle, ts, tt, 0.05)
+        r, st = G.geer_query(gg.handle, s, t, eps, G.geer_params_default(seed=3003), stats=True)
+    # stratified sample: 4 pairs per (eps, pair kind)
+    rng = np.random.default_rng(0)
+    sample = []
+    for e in (0.02, 0.05, 0.1):
+        for half in (0, 1):
+            idx = np.flatnonzero((eps == e) & ((np.arange(nq) >= nq // 2) == bool(half)))
+            sample.extend(rng.choice(idx, 4, replace=False).tolist())
+    return g, s, t, eps, lam, r, st, np.array(sample)
+
+
+def test_rmat22_exact_on_sample(rmat22_run):
+    g, s, t, eps, lam, r, st, sample = rmat22_run
+    deg = g.degrees()
+    assert deg.max() > 100_000  # hub rows span hundreds of segments
+    assert np.all(np.isfinite(r))
+    ex, _ = oracle.exact_cg(g.row_ptr, g.col_idx, s[sample], t[sample], tol=1e-10)
+    assert np.all(np.abs(r[sample] - ex) <= eps[sample])
+
+
+def test_rmat22_replay_on_sample(rmat22_run):
+    g, s, t, eps, lam, r, st, sample = rmat22_run
+    ro, sto = oracle.geer(g.row_ptr, g.col_idx, s[sample], t[sample], eps[sample], lam, seed=3003,
+                          qid=sample)
+    assert np.array_equal(sto["ell"], st["ell"][sample])
+    agree = _agree(st[sample], sto)
+    assert agree.mean() >= 0.9
+    got = r[sample][agree]
+    assert np.all(np.abs(got - ro[agree]) <= 1e-5 * np.maximum(1.0, np.abs(ro[agree])))
+
+
+# ---------------------------------------------------------------------------
+# learned checkpoint on a fresh Chung-Lu n = 2 * 10^6 graph
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def cl2m_run():
+    g = I.chung_lu(2_000_000, 2.1, 20, 1004)
+    s, t = I.uniform_pairs(g.n, 50_000, 2004)
+    with G.Graph(g.n, g.row_ptr32(), g.col_idx) as gg:
+        lam = G.geer_graph_compute_lambda(gg.handle, 400, 1e-8, 7)
+        ts, tt = I.uniform_pairs(g.n, 1024, 2104)
+        G.geer_autotune(gg.handle, ts, tt, 0.05)
+        model = G.Model(path=os.path.join(ROOT, "paper_2312_06123_amd", "data", "scheduler.geermlp"))
+        p = G.geer_params_default(seed=3004, schedule=G.GEER_SCHEDULE_LEARNED, model=model.handle.value)
+        r, st = G.geer_query(gg.handle, s, t, 0.05, p, stats=True)
+    sample = np.random.default_rng(1).choice(np.arange(len(s)), 24, replace=False)
+    return g, s, t, lam, r, st, sample
+
+
+def test_cl2m_learned_applies_and_is_exact(cl2m_run):
+    g, s, t, lam, r, st, sample = cl2m_run
+    assert np.all(np.isfinite(r))
+    assert (st["fallback"] == 0).mean() >= 0.5
+    ex, _ = oracle.exact_cg(g.row_ptr, g.col_idx, s[sample], t[sample], tol=1e-10)
+    assert np.all(np.abs(r[sample] - ex) <= 0.05)
+
+
+def test_cl2m_learned_replay(cl2m_run):
+    g, s, t, lam, r, st, sample = cl2m_run
+    ro, sto = oracle.geer(g.row_ptr, g.col_idx, s[sample], t[sample], 0.05, lam, seed=3004,
+                          schedule="fixed", fixed_lb=st["ell_b"][sample], qid=sample,
+                          tau_per_pair=st["tau"][sample])
+    assert np.array_equal(sto["ell_b"], st["ell_b"][sample])
+    same = (sto["eta1"] == st["eta1"][sample]) & (sto["batches_run"] == st["batches_run"][sample])
+    assert same.mean() >= 0.9
+    assert np.all(np.abs(r[sample][same] - ro[same]) <= 1e-5 * np.maximum(1.0, np.abs(ro[same])))
