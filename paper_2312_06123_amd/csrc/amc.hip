@@ -166,7 +166,7 @@ __device__ __forceinline__ bool lds_row_contains(const int32_t *row, int32_t x)
 }
 
 // Groups up to this many pairs keep their chunk offsets in LDS.
-constexpr int kChunkOffLds = 1024;
+constexpr int kChunkOffLds = 2048;
 constexpr int kXcds = 8;  // accelerator complex dies of an MI355X
 
 template <class T, int RB>

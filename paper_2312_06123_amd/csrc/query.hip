@@ -399,8 +399,11 @@ static int default_col_tile(const geer_graph *g, int vs)
 
 static int default_group_batches(const geer_graph *g, int vs, int64_t nbatches)
 {
+    // up to 32 batches (2,048 pairs) share one AMC phase; slot buffers within
+    // ~96 GB of the 288 GB of HBM (the hop-2 accumulators take at most a
+    // quarter of what is left)
     const double slot_bytes = 3.0 * g->n * kCols * vs;
-    int grp = (int)std::max(1.0, std::min(16.0, 48e9 / slot_bytes));
+    int grp = (int)std::max(1.0, std::min(32.0, 96e9 / slot_bytes));
     return (int)std::min<int64_t>(grp, std::max<int64_t>(nbatches, 1));
 }
 
