@@ -145,6 +145,9 @@ def main() -> int:
                     help="autotuner cache file (a cached entry launches no calibration work)")
     ap.add_argument("--only", choices=["both", "learned", "plain"], default="both",
                     help="time only one schedule (profiling runs)")
+    ap.add_argument("--pairs", choices=["uniform", "edge"], default="uniform",
+                    help="query endpoints: uniform node pairs, or pairs that are edges (the "
+                         "paper's second workload)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -162,7 +165,10 @@ def main() -> int:
 
     log("generating graph")
     g = I.chung_lu(args.nodes, 2.1, 20, 1002)
-    s, t = I.uniform_pairs(g.n, args.queries, 2002)
+    if args.pairs == "edge":
+        s, t = I.edge_pairs(g, args.queries, 2002)
+    else:
+        s, t = I.uniform_pairs(g.n, args.queries, 2002)
     log(f"graph n={g.n} nnz={g.nnz} max_deg={int(g.degrees().max())}")
     gg = G.Graph(g.n, g.row_ptr32(), g.col_idx)
     t0 = time.perf_counter()
@@ -241,7 +247,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {
             "workload": f"chung-lu power-law n={args.nodes} gamma=2.1 mean degree 20, largest "
-                        f"component; {len(s)} uniform pairs; eps={args.eps}; FP32 SMM vectors "
+                        f"component; {len(s)} {args.pairs} pairs; eps={args.eps}; FP32 SMM vectors "
                         f"in 64-pair batches, FP64 accumulation",
             "nodes": g.n, "csr_entries": g.nnz, "queries": len(s), "eps": args.eps,
             "lambda": round(lam, 6), "schedule": head_name,

@@ -72,7 +72,10 @@ enum {
 /* geer_params.flags */
 enum {
     GEER_FLAG_FP64_VECTORS = 1u << 0, /* keep SMM vectors in FP64 instead of FP32 */
-    GEER_FLAG_NO_GRAPH_CAPTURE = 1u << 1 /* run AMC rounds eagerly instead of as a hipGraph */
+    GEER_FLAG_NO_GRAPH_CAPTURE = 1u << 1, /* accepted for compatibility: AMC rounds are always
+                                             launched directly on the stream */
+    GEER_FLAG_PENG_ELL = 1u << 2 /* l by Eq. (old-ell) (Peng et al.'s length, Section 3.1) for every
+                                    pair instead of Eq. (ell): the paper's comparison variant */
 };
 
 typedef struct geer_params {

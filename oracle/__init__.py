@@ -94,7 +94,7 @@ def lib():
                                   _f64p, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
                                   ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_int32, _f64p, ctypes.c_void_p,
-                                  ctypes.c_void_p]
+                                  ctypes.c_void_p, ctypes.c_int32]
         L.oracle_geer.restype = ctypes.c_int
         L.oracle_series.argtypes = [ctypes.c_int64, _i64p, _i32p, ctypes.c_int64, _i32p, _i32p,
                                     _i32p, ctypes.c_int32, _f64p]
@@ -232,13 +232,16 @@ def amc_samples(row_ptr, col_idx, s, t, x, y, lf, seed, q, batch, count) -> np.n
 
 
 def geer(row_ptr, col_idx, s, t, eps, lam, *, tau=5, delta=0.01, seed=0, schedule="greedy",
-         fixed_lb=None, qid=None, threads=None, tau_per_pair=None):
+         fixed_lb=None, qid=None, threads=None, tau_per_pair=None, ell_rule="paper"):
     """Algorithm GEER for arrays of pairs -> (r', stats record array).
 
     schedule: "greedy" (Eq. smm-amc) or "fixed" (exactly min(fixed_lb, l) SMM
     iterations per pair).  ``qid`` gives each pair's index in the walk
-    counter (defaults to its position).
+    counter (defaults to its position).  ell_rule: "paper" (Eq. ell, per
+    pair) or "peng" (Eq. old-ell, the same l for every pair).
     """
+    if ell_rule not in ("paper", "peng"):
+        raise ValueError(ell_rule)
     rp, ci = _csr(row_ptr, col_idx)
     s = np.ascontiguousarray(s, dtype=np.int32)
     t = np.ascontiguousarray(t, dtype=np.int32)
@@ -260,7 +263,7 @@ def geer(row_ptr, col_idx, s, t, eps, lam, *, tau=5, delta=0.01, seed=0, schedul
                            None if flb is None else flb.ctypes.data,
                            None if q is None else q.ctypes.data,
                            int(threads or _default_threads()), out, st.ctypes.data,
-                           None if tp is None else tp.ctypes.data)
+                           None if tp is None else tp.ctypes.data, 1 if ell_rule == "peng" else 0)
     if rc != 0:
         raise MemoryError("oracle_geer failed to allocate")
     return out, st

@@ -309,13 +309,14 @@ static void work_free(work_buf *w)
  * min(fixed_lb, l) SMM iterations.  Returns r'(s, t). */
 static double geer_one(int64_t n, const int64_t *rp, const int32_t *ci, int32_t s, int32_t t,
                        double eps, double lambda, int32_t tau, double delta, uint64_t seed,
-                       uint32_t q, int32_t schedule, int32_t fixed_lb, work_buf *w,
-                       oracle_stats *st)
+                       uint32_t q, int32_t schedule, int32_t fixed_lb, int32_t ell_rule,
+                       work_buf *w, oracle_stats *st)
 {
     memset(st, 0, sizeof(*st));
     if (s == t) return 0.0;                              /* r(s,s) = 0, Section 2.2 */
     double ds = (double)deg_of(rp, s), dt = (double)deg_of(rp, t);
-    int32_t ell = oracle_ell(ds, dt, eps, lambda);
+    /* Eq. (ell), or Eq. (old-ell) for the comparison variant of Section 3.1 */
+    int32_t ell = ell_rule == 1 ? oracle_ell_peng(eps, lambda) : oracle_ell(ds, dt, eps, lambda);
     st->ell = ell;
     double *x = w->x, *y = w->y, *x2 = w->x2, *y2 = w->y2;
     unsigned char *sx = w->sx, *sy = w->sy, *sx2 = w->sx2, *sy2 = w->sy2;
@@ -439,6 +440,7 @@ typedef struct {
     int32_t tau, schedule, max_iter;
     const int32_t *fixed_lb;   /* per query, schedule 1 */
     const int32_t *tau_arr;    /* per query batch count, or NULL for `tau` */
+    int32_t ell_rule;          /* 0: Eq. (ell), 1: Eq. (old-ell) */
     const int32_t *ell_in;     /* per query, series */
     uint64_t seed;
     const int64_t *qid;        /* global query index for the walk counter, or NULL */
@@ -472,7 +474,8 @@ static void *worker(void *arg)
             int32_t flb = j->fixed_lb ? j->fixed_lb[i] : 0;
             int32_t tq = j->tau_arr ? j->tau_arr[i] : j->tau;
             j->r_out[i] = geer_one(j->n, j->rp, j->ci, j->s[i], j->t[i], j->eps[i], j->lambda,
-                                   tq, j->delta, j->seed, q, j->schedule, flb, &w, &st);
+                                   tq, j->delta, j->seed, q, j->schedule, flb, j->ell_rule, &w,
+                                   &st);
             if (j->stats) j->stats[i] = st;
         } else if (j->kind == 1) {
             j->r_out[i] = series_one(j->n, j->rp, j->ci, j->s[i], j->t[i], j->ell_in[i], &w);
@@ -510,11 +513,12 @@ int oracle_geer(int64_t n, const int64_t *rp, const int32_t *ci, int64_t nq,
                 const int32_t *s, const int32_t *t, const double *eps, double lambda,
                 int32_t tau, double delta, uint64_t seed, int32_t schedule,
                 const int32_t *fixed_lb, const int64_t *qid, int32_t threads,
-                double *r_out, oracle_stats *stats, const int32_t *tau_arr)
+                double *r_out, oracle_stats *stats, const int32_t *tau_arr, int32_t ell_rule)
 {
     job_t j;
     memset(&j, 0, sizeof(j));
     j.tau_arr = tau_arr;
+    j.ell_rule = ell_rule;
     j.kind = 0; j.n = n; j.nq = nq; j.rp = rp; j.ci = ci; j.s = s; j.t = t; j.eps = eps;
     j.lambda = lambda; j.tau = tau; j.delta = delta; j.seed = seed; j.schedule = schedule;
     j.fixed_lb = fixed_lb; j.qid = qid; j.r_out = r_out; j.stats = stats;

@@ -231,6 +231,16 @@ __host__ __device__ inline int32_t ell_of(double ds, double dt, double eps, doub
     return c < 0.0 ? 0 : (int32_t)c;
 }
 
+// Eq. (old-ell): Peng et al.'s pair-independent length, log(4 / (eps (1 - lambda)))
+// / log(1 / lambda) - 1, rounded up and clamped at 0 (kept as a variant).
+__host__ __device__ inline int32_t ell_peng_of(double eps, double lambda)
+{
+    if (!(lambda > 0.0)) return 0;
+    const double v = log(4.0 / (eps * (1.0 - lambda))) / log(1.0 / lambda) - 1.0;
+    const double c = ceil(v);
+    return c < 0.0 ? 0 : (int32_t)c;
+}
+
 // Eq. (Delta-st).
 __host__ __device__ inline double psi_of(int32_t lf, double m1s, double m2s, double m1t,
                                          double m2t, double ids, double idt)
@@ -327,6 +337,7 @@ struct QueryCtx {
     uint64_t seed;
     int64_t qid_offset;
     hipStream_t stream;
+    int32_t ell_rule = 0;  // 0: Eq. (ell) per pair, 1: Eq. (old-ell)
 };
 
 geer_status launch_init_queries(geer_graph *g, const QueryCtx &c, const int32_t *d_fixed,

@@ -419,6 +419,8 @@ static geer_status check_params(const geer_params &p)
     if (p.col_tile != 0 && p.col_tile != 32 && p.col_tile != 64 && p.col_tile != 128)
         return fail(GEER_E_INVALID_ARG, "col_tile must be 0, 32, 64 or 128");
     if (p.group_batches < 0) return fail(GEER_E_INVALID_ARG, "group_batches must be >= 0");
+    if (p.flags & ~(uint32_t)(GEER_FLAG_FP64_VECTORS | GEER_FLAG_NO_GRAPH_CAPTURE | GEER_FLAG_PENG_ELL))
+        return fail(GEER_E_INVALID_ARG, "unknown flags");
     if (p.schedule == GEER_SCHEDULE_LEARNED && !p.model)
         return fail(GEER_E_MODEL, "LEARNED schedule needs a model");
     return GEER_OK;
@@ -550,6 +552,7 @@ geer_status geer_query(geer_graph *g, int64_t nq, const int32_t *s, const int32_
     c.schedule = p.schedule;
     c.seed = p.seed;
     c.qid_offset = p.qid_offset;
+    c.ell_rule = (p.flags & GEER_FLAG_PENG_ELL) ? 1 : 0;
     // stage inputs / outputs
     const size_t io_bytes = (size_t)nq * (sizeof(double) + sizeof(int32_t) + sizeof(geer_query_stats)) + 256;
     GEER_TRY(g->ws.io.reserve(io_bytes));
@@ -600,6 +603,7 @@ geer_status geer_query_device(geer_graph *g, int64_t nq, const int32_t *d_s, con
     c.schedule = p.schedule;
     c.seed = p.seed;
     c.qid_offset = p.qid_offset;
+    c.ell_rule = (p.flags & GEER_FLAG_PENG_ELL) ? 1 : 0;
     if (!p.stream) {
         // no stream given: order after all work already queued on the legacy
         // default stream (where the caller's inputs were most likely produced)

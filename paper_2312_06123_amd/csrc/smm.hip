@@ -39,7 +39,7 @@ template <class T> __device__ __forceinline__ void top2_push(T &m1, T &m2, T v)
 __global__ void k_init_queries(QState qs, int64_t nq, const int32_t *__restrict__ row_ptr,
                                int32_t n, double lambda, double delta, int32_t tau,
                                int32_t schedule, const int32_t *__restrict__ fixed,
-                               int32_t forced_hops)
+                               int32_t forced_hops, int32_t ell_rule)
 {
     int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (q >= nq) return;
@@ -82,7 +82,9 @@ __global__ void k_init_queries(QState qs, int64_t nq, const int32_t *__restrict_
     }
     int32_t ds = row_ptr[s + 1] - row_ptr[s], dt = row_ptr[t + 1] - row_ptr[t];
     double ids = 1.0 / ds, idt = 1.0 / dt;
-    int32_t ell = forced_hops >= 0 ? forced_hops : ell_of(ds, dt, eps, lambda);
+    int32_t ell = forced_hops >= 0 ? forced_hops
+                  : ell_rule == 1   ? ell_peng_of(eps, lambda)
+                                    : ell_of(ds, dt, eps, lambda);
     int32_t target = ell;
     if (forced_hops < 0 && schedule == GEER_SCHEDULE_FIXED)
         target = min(max(fixed[q], 0), ell);
@@ -122,7 +124,8 @@ geer_status launch_init_queries(geer_graph *g, const QueryCtx &c, const int32_t 
     if (c.nq == 0) return GEER_OK;
     int blocks = (int)((c.nq + 255) / 256);
     hipLaunchKernelGGL(k_init_queries, dim3(blocks), dim3(256), 0, st, c.qs, c.nq, g->d_row_ptr,
-                       g->n, c.lambda, c.delta, c.tau, c.schedule, d_fixed, forced_hops);
+                       g->n, c.lambda, c.delta, c.tau, c.schedule, d_fixed, forced_hops,
+                       c.ell_rule);
     GEER_HIP(hipGetLastError());
     return GEER_OK;
 }

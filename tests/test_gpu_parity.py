@@ -174,6 +174,54 @@ def test_geer_fp32_coverage_and_replay(cl_graph, schedule):
         assert np.all(np.abs(r - ex) <= eps / 2 + 1e-5)
 
 
+@pytest.mark.parametrize("schedule", ["greedy", "learned"])
+def test_geer_edge_pairs(cl_graph, schedule):
+    # the paper's second workload: (s, t) an edge of the graph (r <= 1)
+    g, lam = cl_graph
+    s, t = I.edge_pairs(g, 200, 14)
+    eps = 0.1
+    with _graph(g, lam) as gg:
+        if schedule == "learned":
+            import os
+            root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+            m = G.Model(path=os.path.join(root, "paper_2312_06123_amd", "data", "scheduler.geermlp"))
+            p = G.geer_params_default(seed=8, schedule=G.GEER_SCHEDULE_LEARNED, model=m.handle.value)
+        else:
+            p = G.geer_params_default(seed=8)
+        r, st = G.geer_query(gg.handle, s, t, eps, p, stats=True)
+    ex, _ = oracle.exact_cg(g.row_ptr, g.col_idx, s, t)
+    assert np.all(ex <= 1.0 + 1e-9)
+    assert np.mean(np.abs(r - ex) <= eps) >= 0.99
+    if schedule == "greedy":
+        ro, sto = oracle.geer(g.row_ptr, g.col_idx, s, t, eps, lam, seed=8)
+    else:
+        ro, sto = oracle.geer(g.row_ptr, g.col_idx, s, t, eps, lam, seed=8, schedule="fixed",
+                              fixed_lb=st["ell_b"], tau_per_pair=st["tau"])
+    assert np.array_equal(st["ell"], sto["ell"])
+    agree = _stats_agree(st, sto)
+    assert agree.mean() >= 0.95
+    assert np.all(np.abs(r[agree] - ro[agree]) <= 1e-5 * np.maximum(1.0, np.abs(ro[agree])))
+
+
+def test_geer_peng_ell_variant(er_graph):
+    # Eq. (old-ell) for every pair (the paper's comparison length), FP64:
+    # same lengths and decisions as the checker's variant, answers to 1e-9
+    g, lam = er_graph
+    s, t = I.uniform_pairs(g.n, 200, 13)
+    with _graph(g, lam) as gg:
+        p = G.geer_params_default(seed=6, flags=G.GEER_FLAG_FP64_VECTORS | G.GEER_FLAG_PENG_ELL)
+        r, st = G.geer_query(gg.handle, s, t, 0.1, p, stats=True)
+        with pytest.raises(G.GeerError) as e:
+            G.geer_query(gg.handle, s, t, 0.1, G.geer_params_default(flags=1 << 7))
+        assert e.value.status == G.GEER_E_INVALID_ARG
+    ro, sto = oracle.geer(g.row_ptr, g.col_idx, s, t, 0.1, lam, seed=6, ell_rule="peng")
+    assert np.all(st["ell"] == oracle.ell_peng(0.1, lam))
+    assert np.array_equal(st["ell"], sto["ell"])
+    agree = _stats_agree(st, sto)
+    assert agree.mean() >= 0.99
+    assert np.all(np.abs(r[agree] - ro[agree]) <= 1e-9)
+
+
 @pytest.mark.parametrize("fp64", [False, True])
 def test_geer_walk_record_widths_identical(cl_graph, fp64):
     # 8-byte packed and 16-byte walk records describe the same walks: every

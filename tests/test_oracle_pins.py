@@ -296,6 +296,30 @@ def test_ell_meets_theorem_bound(g):
             assert l <= oracle.ell_peng(eps, lam)
 
 
+@pytest.mark.parametrize("g", _small_graphs()[:4], ids=lambda g: g.name)
+def test_peng_ell_bound_and_geer_variant(g):
+    # Eq. (old-ell): one length for every pair, also within eps/2 of r; at
+    # d(s) = d(t) = 1 it coincides with Eq. (ell)
+    lam = oracle.lambda_dense(g.row_ptr, g.col_idx)
+    rng = np.random.default_rng(3)
+    for eps in (0.5, 0.1, 0.02):
+        lp = oracle.ell_peng(eps, lam)
+        assert lp == oracle.ell(1, 1, eps, lam)
+        for _ in range(6):
+            s, t = rng.choice(g.n, 2, replace=False)
+            r = oracle.exact_pinv(g.row_ptr, g.col_idx, s, t)
+            rl = oracle.series(g.row_ptr, g.col_idx, [s], [t], [lp])[0]
+            assert abs(r - rl) <= eps / 2 + 1e-12
+    # GEER with the variant length: every pair gets l = Eq. (old-ell), and the
+    # SMM-only run (l_b = l) is the truncated series at that length
+    s, t = (np.array(x, dtype=np.int32) for x in zip(*[rng.choice(g.n, 2, replace=False) for _ in range(10)]))
+    r, st = oracle.geer(g.row_ptr, g.col_idx, s, t, 0.1, lam, seed=4, ell_rule="peng",
+                        schedule="fixed", fixed_lb=10 ** 6)
+    assert np.all(st["ell"] == oracle.ell_peng(0.1, lam))
+    rl = oracle.series(g.row_ptr, g.col_idx, s, t, st["ell"])
+    assert np.allclose(r, rl, rtol=1e-12, atol=1e-14)
+
+
 def test_ell_monotone_and_clamped():
     assert oracle.ell(1, 1, 10.0, 0.5) == 0
     assert oracle.ell(3, 4, 0.1, 0.0) == 0
