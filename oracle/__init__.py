@@ -1,7 +1,7 @@
 """CPU FP64 checker for GEER (Yang & Tang, pairwise effective resistance).
 
 TEST INFRASTRUCTURE ONLY.  This package is the plain, slow reference the GPU
-library is judged against.  Only the test-suite, the smoke check and the
+library is checked against.  Only the test-suite, the smoke check and the
 benchmark's CPU-baseline leg may import it; the product path never does.  It
 shares no code with the GPU library and does not import it.
 

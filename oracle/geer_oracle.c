@@ -3,7 +3,7 @@
  * (Yang & Tang, "Efficient Estimation of Pairwise Effective Resistance").
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference that the
- * GPU library is judged against.  It shares no code with the GPU library and
+ * GPU library is checked against.  It shares no code with the GPU library and
  * must only be called from the test-suite, the smoke check and the
  * benchmark's CPU-baseline leg.  Nothing in the product path may load it.
  *
