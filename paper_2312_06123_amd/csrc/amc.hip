@@ -20,7 +20,7 @@ template <> struct Val2<double> { using type = double2; };
 // the graph instead of read from the vector buffer: on N(s) the hop-1 vector
 // is 1/d(u), elsewhere 0, so membership in the (cache-resident) sorted row of
 // s gives the same value as the random read of the buffer.
-constexpr int32_t kMemberRowMax = 64;
+constexpr int32_t kMemberRowMax = 256;
 
 __device__ __forceinline__ bool one_hop_from_graph(int32_t lb, int32_t ds, int32_t dt)
 {
@@ -181,17 +181,18 @@ __global__ __launch_bounds__(256) void k_walk(QState qs, int64_t q0, int nq, int
                                               double2 *__restrict__ zpart)
 {
     using T2 = typename Val2<T>::type;
-    __shared__ int64_t s_off[kChunkOffLds + 1];
+    // chunk offsets in LDS as 32-bit values when they fit
+    __shared__ int32_t s_off[kChunkOffLds + 1];
     // per wave: the sorted rows of s and t of its current chunk's pair
     __shared__ int32_t s_rows[4][2][kMemberRowMax];
-    const bool lds_off = nq <= kChunkOffLds;
+    const int64_t total = *total_p;
+    const bool lds_off = nq <= kChunkOffLds && total < (int64_t(1) << 31);
     if (lds_off)
-        for (int i = threadIdx.x; i <= nq; i += blockDim.x) s_off[i] = chunk_off[i];
+        for (int i = threadIdx.x; i <= nq; i += blockDim.x) s_off[i] = (int32_t)chunk_off[i];
     __syncthreads();
-    const int64_t *off = lds_off ? s_off : chunk_off;
+    auto off = [&](int i) -> int64_t { return lds_off ? (int64_t)s_off[i] : chunk_off[i]; };
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int64_t total = *total_p;
     // Blocks are dealt to the 8 XCDs round-robin; XCD x takes the x-th eighth
     // of the chunks (chunks are ordered by batch slot), so the vector rows its
     // walks revisit belong to few slots and can stay in that XCD's L2.
@@ -206,12 +207,12 @@ __global__ __launch_bounds__(256) void k_walk(QState qs, int64_t q0, int nq, int
         int lo = 0, hi = nq;
         while (hi - lo > 1) {
             int mid = (lo + hi) >> 1;
-            if (off[mid] <= c) lo = mid;
+            if (off(mid) <= c) lo = mid;
             else hi = mid;
         }
         const int64_t q = qs.ord[q0 + lo];
         const int64_t eta = qs.eta1[q] << round;
-        const int64_t k = (c - off[lo]) * kPairsPerChunk + (lane >> 1);
+        const int64_t k = (c - off(lo)) * kPairsPerChunk + (lane >> 1);
         const bool valid = k < eta;
         const int32_t s = qs.s[q], t = qs.t[q];
         const int32_t lf = qs.lf[q];
@@ -225,8 +226,10 @@ __global__ __launch_bounds__(256) void k_walk(QState qs, int64_t q0, int nq, int
         if (member) {
             // the wave's previous reads of s_rows have completed (their values
             // were consumed), so the rows can be overwritten in place
-            s_rows[wv][0][lane] = lane < ds ? col_idx[bs + lane] : INT32_MAX;
-            s_rows[wv][1][lane] = lane < dt ? col_idx[bt + lane] : INT32_MAX;
+            for (int i = lane; i < kMemberRowMax; i += 64) {
+                s_rows[wv][0][i] = i < ds ? col_idx[bs + i] : INT32_MAX;
+                s_rows[wv][1][i] = i < dt ? col_idx[bt + i] : INT32_MAX;
+            }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");

@@ -203,6 +203,27 @@ def test_geer_edge_pairs(cl_graph, schedule):
     assert np.all(np.abs(r[agree] - ro[agree]) <= 1e-5 * np.maximum(1.0, np.abs(ro[agree])))
 
 
+def test_geer_batching_invariance(cl_graph):
+    # A pair's estimate does not depend on how pairs are batched, grouped or
+    # tiled: walks are keyed by the pair's index, its chunk partials are summed
+    # in a fixed order, hop 2 is exact and the dense rows sum their neighbours
+    # in CSR order.  (Batches are kept small enough that hop 2 takes the
+    # sparse path in every configuration.)
+    g, lam = cl_graph
+    s, t = I.uniform_pairs(g.n, 240, 15)
+    s[:30], t[:30] = I.edge_pairs(g, 30, 16)
+    out = []
+    with _graph(g, lam) as gg:
+        for bq, gb, tile in ((16, 1, 0), (32, 4, 32), (24, 3, 64), (8, 40, 128)):
+            p = G.geer_params_default(seed=10, batch_queries=bq, group_batches=gb, col_tile=tile)
+            out.append(G.geer_query(gg.handle, s, t, 0.1, p, stats=True))
+    r0, st0 = out[0]
+    for r, st in out[1:]:
+        assert np.array_equal(r, r0)
+        for f in ("ell", "ell_b", "tau", "eta1", "batches_run", "walk_pairs", "supp_sum"):
+            assert np.array_equal(st[f], st0[f]), f
+
+
 def test_geer_peng_ell_variant(er_graph):
     # Eq. (old-ell) for every pair (the paper's comparison length), FP64:
     # same lengths and decisions as the checker's variant, answers to 1e-9
