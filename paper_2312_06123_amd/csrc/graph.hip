@@ -342,6 +342,15 @@ geer_status geer_graph_create(int32_t n, const int32_t *row_ptr, const int32_t *
         delete g;
         return fail(GEER_E_DEVICE, "hipStreamCreate failed");
     }
+    bool ev_ok = hipStreamCreateWithFlags(&g->stream2, hipStreamNonBlocking) == hipSuccess;
+    for (int i = 0; i < 2 && ev_ok; ++i)
+        ev_ok = hipEventCreateWithFlags(&g->ev_smm[i], hipEventDisableTiming) == hipSuccess &&
+                hipEventCreateWithFlags(&g->ev_clean[i], hipEventDisableTiming) == hipSuccess;
+    ev_ok = ev_ok && hipEventCreateWithFlags(&g->ev_done, hipEventDisableTiming) == hipSuccess;
+    if (!ev_ok) {
+        geer_graph_destroy(g);
+        return fail(GEER_E_DEVICE, "stream or event creation failed");
+    }
     geer_status st = build_graph(g, row_ptr, col_idx);
     if (st != GEER_OK) {
         std::string msg = geer_last_error();
@@ -373,6 +382,13 @@ void geer_graph_destroy(geer_graph *g)
     }
     for (hipEvent_t e : g->prof.spare) (void)hipEventDestroy(e);
     if (g->prof.d_counters) (void)hipFree(g->prof.d_counters);
+    if (g->stream2) (void)hipStreamSynchronize(g->stream2);
+    for (int i = 0; i < 2; ++i) {
+        if (g->ev_smm[i]) (void)hipEventDestroy(g->ev_smm[i]);
+        if (g->ev_clean[i]) (void)hipEventDestroy(g->ev_clean[i]);
+    }
+    if (g->ev_done) (void)hipEventDestroy(g->ev_done);
+    if (g->stream2) (void)hipStreamDestroy(g->stream2);
     if (g->stream) (void)hipStreamDestroy(g->stream);
     delete g;
 }

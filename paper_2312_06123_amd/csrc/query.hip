@@ -115,10 +115,11 @@ static geer_status set_words(uint64_t *dst, const uint64_t *src, size_t n, hipSt
 }
 
 struct SlotView {
-    char *pool;
+    char *pool;      // slot 0 of this slot set
     uint32_t *bits;
     size_t n;
     int vs;
+    int k0 = 0;      // index of slot 0 among all slots (per-slot flags and statistics)
     void *buf(int slot, int which) const
     {
         return pool + ((size_t)slot * 3 + which) * n * kCols * vs;
@@ -163,8 +164,8 @@ static SlotArgs slot_args(geer_graph *g, const SlotView &sv, const SlotMeta &sm,
     a.bits = sv.bits;
     a.buf_elems = (int64_t)sv.n * kCols;
     a.buf_words = (int64_t)sv.n * kBitWords;
-    a.cs = g->ws.colstat.as<double>();
-    a.hpart = g->ws.hpart.as<double>();
+    a.cs = g->ws.colstat.as<double>() + (size_t)sv.k0 * 3 * kCols;
+    a.hpart = g->ws.hpart.as<double>() + (size_t)sv.k0 * 3 * kPushSplit * kCols;
     a.meta = sm.base;
     return a;
 }
@@ -248,10 +249,10 @@ static geer_status run_level(geer_graph *g, const QueryCtx &c, const SlotView &s
         }
         if (any) {
             for (int k = 0; k < nbat; ++k)
-                if (sparse[k] && ws.a_dirty[k]) {
+                if (sparse[k] && ws.a_dirty[sv.k0 + k]) {
                     GEER_TRY(launch_zero(g, sv.buf(k, 1), (size_t)g->n * kCols * sv.vs, c.stream));
                     GEER_TRY(launch_zero(g, sv.bw(k, 1), (size_t)g->n * kBitWords * 4, c.stream));
-                    ws.a_dirty[k] = 0;
+                    ws.a_dirty[sv.k0 + k] = 0;
                 }
             GEER_TRY(set_words(sm.h2(0), words.data(), words.size(), c.stream));
             GEER_TRY(launch_zero(g, sa.hpart, (size_t)nbat * 3 * kPushSplit * kCols * sizeof(double),
@@ -291,7 +292,7 @@ static geer_status run_level(geer_graph *g, const QueryCtx &c, const SlotView &s
         a.col0 = 0;
         a.col_tile = pick_tile(g, col_tile, hm[k], sv.vs);
         GEER_TRY(launch_hop_dense(g, a, sv.vs, c.stream));
-        if (wout == 1) ws.a_dirty[k] = 1;
+        if (wout == 1) ws.a_dirty[sv.k0 + k] = 1;
     }
     return launch_epilogue_group(g, c, sa, nbat, hop, wout, sv.vs, c.stream);
 }
@@ -307,7 +308,7 @@ static geer_status cleanup_group(geer_graph *g, const QueryCtx &c, const SlotVie
         h1 |= recs[k].hop1;
         // a dense hop that wrote A later makes it dirty: it is zeroed in full
         // before its next sparse use instead
-        if (recs[k].hop2_sparse && !g->ws.a_dirty[k]) {
+        if (recs[k].hop2_sparse && !g->ws.a_dirty[sv.k0 + k]) {
             words[k] = recs[k].hop2_sparse;
             h2 = true;
         }
@@ -397,13 +398,14 @@ static int default_col_tile(const geer_graph *g, int vs)
     return 32;
 }
 
-static int default_group_batches(const geer_graph *g, int vs, int64_t nbatches)
+static int default_group_batches(const geer_graph *g, int vs, int64_t nbatches, int sets)
 {
-    // up to 32 batches (2,048 pairs) share one AMC phase; slot buffers within
-    // ~96 GB of the 288 GB of HBM (the hop-2 accumulators take at most a
-    // quarter of what is left)
+    // up to 32 batches (2,048 pairs) share one AMC phase; the slot buffers of
+    // all slot sets within ~96 GB (one set) or ~128 GB (two sets) of the
+    // 288 GB of HBM (the hop-2 accumulators take at most a quarter of the rest)
     const double slot_bytes = 3.0 * g->n * kCols * vs;
-    int grp = (int)std::max(1.0, std::min(32.0, 96e9 / slot_bytes));
+    const double budget = sets == 2 ? 128e9 : 96e9;
+    int grp = (int)std::max(1.0, std::min(32.0, budget / (sets * slot_bytes)));
     return (int)std::min<int64_t>(grp, std::max<int64_t>(nbatches, 1));
 }
 
@@ -437,10 +439,15 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
     const int vs = (p.flags & GEER_FLAG_FP64_VECTORS) ? 8 : 4;
     const int B = p.batch_queries ? p.batch_queries : kMaxPairs;
     const int64_t nbatches = (c.nq + B - 1) / B;
-    const int G = std::min(1024, p.group_batches ? p.group_batches : default_group_batches(g, vs, nbatches));
+    // one slot set when every batch fits one group, else two: group i + 1's
+    // SMM fills one set while group i's AMC phase reads the other
+    int G = std::min(1024, p.group_batches ? p.group_batches : default_group_batches(g, vs, nbatches, 1));
+    const int sets = nbatches > G ? 2 : 1;
+    if (sets == 2 && !p.group_batches) G = default_group_batches(g, vs, nbatches, 2);
     const int col_tile = p.col_tile ? -p.col_tile : default_col_tile(g, vs);
-    GEER_TRY(ensure_slots(g, G, vs));
-    GEER_TRY(g->ws.meta.reserve((6 * (size_t)G + (size_t)G * (max_hops + 2)) * 8 + 64));
+    GEER_TRY(ensure_slots(g, sets * G, vs));
+    const size_t meta_words = 6 * (size_t)G + (size_t)G * (max_hops + 2);
+    GEER_TRY(g->ws.meta.reserve((sets * meta_words) * 8 + 64));
     GEER_TRY(launch_init_queries(g, c, d_fixed, -1, c.stream));
     const bool learned = p.schedule == GEER_SCHEDULE_LEARNED;
     if (learned) c.tau = std::max(c.tau, kLearnedTauMax);
@@ -470,31 +477,69 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
         while (n_static < c.nq && !fb[ord[n_static]]) ++n_static;
     }
     GEER_HIP(hipMemcpyAsync(c.qs.ord, ord.data(), c.nq * sizeof(int32_t), hipMemcpyHostToDevice, c.stream));
-    SlotView sv{g->ws.pool.as<char>(), g->ws.bits.as<uint32_t>(), (size_t)g->n, vs};
-    SlotMeta sm{g->ws.meta.as<uint64_t>(), G};
-    std::vector<BatchRec> recs(G);
+    // groups in order: the static phase (known depths), then the greedy one
+    struct Job {
+        GroupPlan gp;
+        bool is_static;
+        int set;
+    };
+    std::vector<Job> jobs;
     for (int phase = 0; phase < 2; ++phase) {
         const bool is_static = phase == 0;
         const int64_t pb = is_static ? 0 : n_static, pe = is_static ? n_static : c.nq;
         const int64_t nbat_phase = (pe - pb + B - 1) / B;
         for (int64_t b0 = 0; b0 < nbat_phase; b0 += G) {
-            GroupPlan gp;
-            gp.p0 = pb + b0 * B;
-            gp.nbat = std::min<int64_t>(nbat_phase, b0 + G) - b0;
-            gp.pend = pe;
-            gp.B = B;
-            sm.base = g->ws.meta.as<uint64_t>();
-            GEER_TRY(smm_group(g, c, sv, sm, gp, is_static, target.data(), h_s, h_t, ord.data(),
-                               col_tile, max_hops, recs));
-            sm.base = g->ws.meta.as<uint64_t>();
-            AmcGroup grp;
-            grp.q0 = gp.p0;
-            grp.nq = std::min<int64_t>(pe, gp.p0 + gp.nbat * B) - grp.q0;
-            grp.pool = sv.pool;
-            grp.value_size = vs;
-            GEER_TRY(amc_phase(g, c, grp, c.stream, p.walk_ilp));
-            GEER_TRY(cleanup_group(g, c, sv, sm, slot_args(g, sv, sm, gp), (int)gp.nbat, recs));
+            Job jb;
+            jb.gp.p0 = pb + b0 * B;
+            jb.gp.nbat = std::min<int64_t>(nbat_phase, b0 + G) - b0;
+            jb.gp.pend = pe;
+            jb.gp.B = B;
+            jb.is_static = is_static;
+            jb.set = (int)(jobs.size() % sets);
+            jobs.push_back(jb);
         }
+    }
+    const size_t set_vals = (size_t)G * 3 * g->n * kCols, set_words = (size_t)G * 3 * g->n * kBitWords;
+    auto view = [&](int set) {
+        SlotView v{g->ws.pool.as<char>() + set * set_vals * vs, g->ws.bits.as<uint32_t>() + set * set_words,
+                   (size_t)g->n, vs, set * G};
+        return v;
+    };
+    auto meta = [&](int set) { return SlotMeta{g->ws.meta.as<uint64_t>() + set * meta_words, G}; };
+    std::vector<std::vector<BatchRec>> recs(sets, std::vector<BatchRec>(G));
+    hipStream_t sA = c.stream, sB = sets == 2 ? g->stream2 : c.stream;
+    QueryCtx cB = c;
+    cB.stream = sB;
+    // AMC phase and buffer cleanup of job i (on sB, after its SMM on sA)
+    auto amc = [&](size_t i) -> geer_status {
+        const Job &jb = jobs[i];
+        const SlotView v = view(jb.set);
+        const SlotMeta m = meta(jb.set);
+        if (sB != sA) GEER_HIP(hipStreamWaitEvent(sB, g->ev_smm[jb.set], 0));
+        AmcGroup grp;
+        grp.q0 = jb.gp.p0;
+        grp.nq = std::min<int64_t>(jb.gp.pend, jb.gp.p0 + jb.gp.nbat * B) - grp.q0;
+        grp.pool = v.pool;
+        grp.value_size = vs;
+        GEER_TRY(amc_phase(g, cB, grp, sB, p.walk_ilp));
+        GEER_TRY(cleanup_group(g, cB, v, m, slot_args(g, v, m, jb.gp), (int)jb.gp.nbat, recs[jb.set]));
+        if (sB != sA) GEER_HIP(hipEventRecord(g->ev_clean[jb.set], sB));
+        return GEER_OK;
+    };
+    // the AMC phase of job i - 1 is queued (its chunk bound read first) before
+    // the SMM of job i, so both run at once on the two slot sets
+    for (size_t i = 0; i <= jobs.size(); ++i) {
+        if (i >= 1) GEER_TRY(amc(i - 1));
+        if (i == jobs.size()) break;
+        const Job &jb = jobs[i];
+        if (sets == 2 && i >= 2) GEER_HIP(hipStreamWaitEvent(sA, g->ev_clean[jb.set], 0));
+        GEER_TRY(smm_group(g, c, view(jb.set), meta(jb.set), jb.gp, jb.is_static, target.data(), h_s,
+                           h_t, ord.data(), col_tile, max_hops, recs[jb.set]));
+        if (sets == 2) GEER_HIP(hipEventRecord(g->ev_smm[jb.set], sA));
+    }
+    if (sets == 2) {
+        GEER_HIP(hipEventRecord(g->ev_done, sB));
+        GEER_HIP(hipStreamWaitEvent(sA, g->ev_done, 0));
     }
     return GEER_OK;
 }
