@@ -352,8 +352,10 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float *__restrict__ para
 
 __global__ void k_learned_apply(QState qs, int64_t nq, const float *__restrict__ feat,
                                 const float *__restrict__ norm, const uint16_t *__restrict__ pb,
-                                const int32_t *__restrict__ row_ptr, double delta, float zmax,
-                                int32_t tau_max)
+                                const int32_t *__restrict__ row_ptr,
+                                const int32_t *__restrict__ min_nbr_deg,
+                                const int64_t *__restrict__ nbr_work, double rho2, double delta,
+                                float zmax, int32_t tau_max)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nq) return;
@@ -380,8 +382,29 @@ __global__ void k_learned_apply(QState qs, int64_t nq, const float *__restrict__
         qs.fallback[q] = 1;  // greedy switch of Eq. (smm-amc) with the default tau
         return;
     }
-    const int32_t lb = (int32_t)min((double)ell, max(0.0, rint((double)o[0])));
+    int32_t lb = (int32_t)min((double)ell, max(0.0, rint((double)o[0])));
     const int32_t tau = (int32_t)min((double)tau_max, max(1.0, rint((double)o[1])));
+    // Cost guards on the predicted depth (regression outputs near a rounding
+    // boundary are occasionally far off, and one such pair can cost more
+    // walks than thousands of others):
+    //  * hop 1 is one scatter per column, so at least one product is taken;
+    //  * stopping after one product is rejected when even the first batch of
+    //    walks would cost more than hop 2.  After one product the largest
+    //    entry of the s-vector is 1/(smallest degree in N(s)) exactly and the
+    //    second largest is >= 0, so psi, eta* and eta_1 below are lower
+    //    bounds; hop 2 costs rho2 * (sum of neighbour degrees of s and t)
+    //    walk-step equivalents.
+    if (ell >= 1 && lb < 1) lb = 1;
+    if (lb == 1 && ell >= 2) {
+        const int32_t s = qs.s[q], t = qs.t[q];
+        const double ids = 1.0 / (row_ptr[s + 1] - row_ptr[s]);
+        const double idt = 1.0 / (row_ptr[t + 1] - row_ptr[t]);
+        const int32_t lf = ell - 1;
+        const double psi_lo = psi_of(lf, 1.0 / min_nbr_deg[s], 0.0, 1.0 / min_nbr_deg[t], 0.0, ids, idt);
+        const double first = 2.0 * lf * (double)eta1_of(eta_star_of(psi_lo, eps, tau, delta), tau);
+        const double hop2 = rho2 * (double)(nbr_work[s] + nbr_work[t]);
+        if (first > hop2) lb = 2;
+    }
     qs.fallback[q] = 0;
     qs.tau_q[q] = tau;
     qs.lb_target[q] = lb;
@@ -459,7 +482,8 @@ geer_status launch_learned(geer_graph *g, const QueryCtx &c, const geer_model *m
     GEER_HIP(hipGetLastError());
     tok = prof_begin(g, st);
     hipLaunchKernelGGL(k_learned_apply, dim3((int)((c.nq + 255) / 256)), dim3(256), 0, st, c.qs, c.nq,
-                       d_feat, m->d_norm, m->d_bf16, g->d_row_ptr, c.delta, 8.0f, tau_max);
+                       d_feat, m->d_norm, m->d_bf16, g->d_row_ptr, g->d_min_nbr_deg, g->d_nbr_work,
+                       g->rho2, c.delta, 8.0f, tau_max);
     prof_end(g, tok, PK_MLP, 0.0, 0.0, st);
     GEER_HIP(hipGetLastError());
     return GEER_OK;
