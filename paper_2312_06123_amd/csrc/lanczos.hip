@@ -21,41 +21,66 @@ namespace geer {
 __global__ __launch_bounds__(256) void k_norm_spmv(int32_t n, const int32_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col_idx,
                                                    const double *__restrict__ isd,
-                                                   const double *__restrict__ x,
+                                                   const double *__restrict__ xs,
                                                    double *__restrict__ y)
 {
+    // xs = D^{-1/2} x was formed beforehand, so each CSR entry gathers one value
     const int lane = threadIdx.x & 63;
     for (int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); v < n;
          v += (int64_t)gridDim.x * 4) {
         const int32_t b = row_ptr[v], e = row_ptr[v + 1];
         double acc = 0.0;
-        for (int32_t k = b + lane; k < e; k += 64) {
-            const int32_t u = col_idx[k];
-            acc += isd[u] * x[u];
-        }
+        for (int32_t k = b + lane; k < e; k += 64) acc += xs[col_idx[k]];
         for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
         if (lane == 0) y[v] = isd[v] * acc;
     }
 }
 
-// out[k] = <V_k, w> for k < m (V stored vector-major, stride n); one block per k.
-__global__ __launch_bounds__(1024) void k_dots(int32_t n, const double *__restrict__ V, int m,
-                                               const double *__restrict__ w,
-                                               double *__restrict__ out)
+__global__ __launch_bounds__(256) void k_mul(int32_t n, const double *__restrict__ a,
+                                             const double *__restrict__ x, double *__restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = a[i] * x[i];
+}
+
+// <V_k, w> for k < m (V stored vector-major, stride n), in two passes with a
+// fixed summation order: block b sums its slice of every product into
+// part[k * nb + b], then one block per k adds the nb partials.
+constexpr int kDotBlocks = 512;
+
+__global__ __launch_bounds__(256) void k_dots_partial(int32_t n, const double *__restrict__ V, int m,
+                                                      const double *__restrict__ w,
+                                                      double *__restrict__ part)
+{
+    const int b = blockIdx.x, nb = gridDim.x;
+    const int64_t per = ((int64_t)n + nb - 1) / nb;
+    const int64_t i0 = (int64_t)b * per, i1 = min((int64_t)n, i0 + per);
+    __shared__ double sh[4];
+    for (int k = 0; k < m; ++k) {
+        const double *vk = V + (size_t)k * n;
+        double acc = 0.0;
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) acc += vk[i] * w[i];
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) part[(size_t)k * nb + b] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_dots_final(int nb, int m, const double *__restrict__ part,
+                                                    double *__restrict__ out)
 {
     const int k = blockIdx.x;
     if (k >= m) return;
-    const double *vk = V + (size_t)k * n;
     double acc = 0.0;
-    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) acc += vk[i] * w[i];
-    __shared__ double sh[1024];
-    sh[threadIdx.x] = acc;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += part[(size_t)k * nb + i];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    __shared__ double sh[4];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
     __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[k] = sh[0];
+    if (threadIdx.x == 0) out[k] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
 // w -= sum_k c[k] V_k, then optionally write w * scale to dst.
@@ -162,11 +187,15 @@ extern "C" geer_status geer_graph_compute_lambda(geer_graph *g, int32_t max_iter
     // device memory: basis (u + m_max + 1 vectors), w, isd, coefficient buffer
     DevBuf basis, work;
     GEER_TRY(basis.reserve((size_t)(m_max + 2) * n * sizeof(double)));
-    GEER_TRY(work.reserve((size_t)2 * n * sizeof(double) + (size_t)(m_max + 2) * sizeof(double)));
+    const int nb = std::max(1, std::min(kDotBlocks, (n + 255) / 256));
+    GEER_TRY(work.reserve((size_t)3 * n * sizeof(double) + (size_t)(m_max + 2) * sizeof(double) +
+                          (size_t)(m_max + 2) * nb * sizeof(double)));
     double *V = basis.as<double>();          // V[0] = u (deflated vector), V[1..] Lanczos basis
     double *w = work.as<double>();
     double *isd = w + n;
     double *coef = isd + n;
+    double *part = coef + (m_max + 2);
+    double *xs = part + (size_t)(m_max + 2) * nb;  // D^{-1/2} V_j for the product
     std::vector<int32_t> rp(n + 1);
     GEER_HIP(hipMemcpy(rp.data(), g->d_row_ptr, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
     std::vector<double> h_isd(n), h_u(n), h_v(n);
@@ -193,13 +222,18 @@ extern "C" geer_status geer_graph_compute_lambda(geer_graph *g, int32_t max_iter
     GEER_HIP(hipMemcpy(w, h_v.data(), n * sizeof(double), hipMemcpyHostToDevice));
     const int eb = std::max(1, std::min(g->num_cus * 8, (n + 255) / 256));
     const int sb = std::max(1, std::min(g->num_cus * 8, (n + 3) / 4));
+    // coef[k] = <Vp_k, x> for k < m
+    auto dots = [&](const double *Vp, int m, const double *x) {
+        hipLaunchKernelGGL(k_dots_partial, dim3(nb), dim3(256), 0, st, n, Vp, m, x, part);
+        hipLaunchKernelGGL(k_dots_final, dim3(m), dim3(256), 0, st, nb, m, part, coef);
+    };
     auto orthonormalise = [&](int nvec, double *beta_out) -> geer_status {
         // two passes of classical Gram-Schmidt against V[0..nvec-1]
         for (int pass = 0; pass < 2; ++pass) {
-            hipLaunchKernelGGL(k_dots, dim3(nvec), dim3(1024), 0, st, n, V, nvec, w, coef);
+            dots(V, nvec, w);
             hipLaunchKernelGGL(k_subtract, dim3(eb), dim3(256), 0, st, n, V, nvec, coef, w);
         }
-        hipLaunchKernelGGL(k_dots, dim3(1), dim3(1024), 0, st, n, w, 1, w, coef);
+        dots(w, 1, w);
         GEER_HIP(hipGetLastError());
         double nn = 0.0;
         GEER_HIP(hipMemcpyAsync(&nn, coef, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -216,9 +250,10 @@ extern "C" geer_status geer_graph_compute_lambda(geer_graph *g, int32_t max_iter
     int m = 0;
     for (int j = 0; j < m_max; ++j) {
         // w = N V_j, then orthogonalise against u and V_1..V_j (alpha = <V_j, w> first)
+        hipLaunchKernelGGL(k_mul, dim3(eb), dim3(256), 0, st, n, isd, V + (size_t)(j + 1) * n, xs);
         hipLaunchKernelGGL(k_norm_spmv, dim3(sb), dim3(256), 0, st, n, g->d_row_ptr, g->d_col_idx,
-                           isd, V + (size_t)(j + 1) * n, w);
-        hipLaunchKernelGGL(k_dots, dim3(1), dim3(1024), 0, st, n, V + (size_t)(j + 1) * n, 1, w, coef);
+                           isd, xs, w);
+        dots(V + (size_t)(j + 1) * n, 1, w);
         GEER_HIP(hipGetLastError());
         double a = 0.0;
         GEER_HIP(hipMemcpyAsync(&a, coef, sizeof(double), hipMemcpyDeviceToHost, st));
