@@ -88,16 +88,21 @@ typedef struct geer_params {
     const geer_model *model;     /* LEARNED: the scheduler */
     void *stream;                /* hipStream_t to run on, or NULL for the library's stream */
     int32_t batch_queries;       /* queries per SMM batch, 1..64 (0 = 64) */
-    int32_t col_tile;            /* SpMM column tile 16/32/64/128 (0 = autotuned/default) */
-    int32_t walk_ilp;            /* walks interleaved per lane 1/2/4 (0 = autotuned/default) */
-    int32_t group_batches;       /* SMM batches resident before each AMC phase (0 = auto) */
+    int32_t col_tile;            /* dense SpMM column tile 32/64/128 (0 = autotuned per hop) */
+    int32_t walk_ilp;            /* 0 or 1: one walk per lane (the walk kernel is bound by random
+                                    line fetches, which interleaving more walks per lane does not
+                                    raise); other values are rejected */
+    int32_t group_batches;       /* batches per group: their SMM runs, then one AMC phase for all
+                                    of them (0 = auto, at most 32).  With more than one group, two
+                                    slot sets alternate and a group's AMC phase overlaps the next
+                                    group's SMM on a second library stream */
     uint32_t flags;              /* GEER_FLAG_* */
     int32_t reserved[7];
 } geer_params;
 
 /* Per-query record (optional output of geer_query). */
 typedef struct geer_query_stats {
-    int32_t ell;          /* Eq. (ell) */
+    int32_t ell;          /* Eq. (ell), or Eq. (old-ell) with GEER_FLAG_PENG_ELL */
     int32_t ell_b;        /* SMM products performed */
     int32_t tau;          /* AMC batches allowed */
     int32_t batches_run;  /* AMC batches performed */
@@ -217,8 +222,11 @@ geer_status geer_amc(geer_graph *g, int32_t s, int32_t t, const double *x, const
  * pair, the SMM depth l_b, the AMC batch count tau and log10 of the absolute
  * error.  Used by GEER_SCHEDULE_LEARNED; pairs whose predicted error exceeds
  * eps or whose features leave the training range use the greedy switch of
- * Eq. (smm-amc).  The estimator (l, eta*, the stop rule, delta) is unchanged,
- * so the guarantee of Theorem 3.2 holds for any prediction.
+ * Eq. (smm-amc).  The predicted depth is guarded by exact graph quantities: at
+ * least one product when l >= 1, and two when a lower bound of the first walk
+ * batch after one product exceeds the hop-2 cost (rho2 times the neighbour
+ * degree sums of s and t).  The estimator (l, eta*, the stop rule, delta) is
+ * unchanged, so the guarantee of Theorem 3.2 holds for any prediction.
  * Parameters: FP32 master copy, BF16 copy for inference; layout row-major
  * W1[F][64], b1[64], W2[64][64], b2[64], W3[64][3], b3[3].
  * Features (raw, per pair): log2 d(s), log2 d(t), l/16, log2(1 + sum of the

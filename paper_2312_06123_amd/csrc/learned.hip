@@ -20,7 +20,6 @@ constexpr int kF = GEER_MLP_FEATURES;  // input features
 constexpr int kH = GEER_MLP_HIDDEN;    // hidden width
 constexpr int kO = GEER_MLP_OUTPUTS;   // outputs: l_b, tau, log10 error
 constexpr int kP = kF * kH + kH + kH * kH + kH + kH * kO + kO;  // parameter count
-constexpr int kTrainBatch = 128;
 
 // parameter layout (row-major [in][out])
 constexpr int oW1 = 0, oB1 = oW1 + kF * kH, oW2 = oB1 + kH, oB2 = oW2 + kH * kH,

@@ -421,6 +421,7 @@ static geer_status check_params(const geer_params &p)
     if (p.col_tile != 0 && p.col_tile != 32 && p.col_tile != 64 && p.col_tile != 128)
         return fail(GEER_E_INVALID_ARG, "col_tile must be 0, 32, 64 or 128");
     if (p.group_batches < 0) return fail(GEER_E_INVALID_ARG, "group_batches must be >= 0");
+    if (p.walk_ilp != 0 && p.walk_ilp != 1) return fail(GEER_E_INVALID_ARG, "walk_ilp must be 0 or 1");
     if (p.flags & ~(uint32_t)(GEER_FLAG_FP64_VECTORS | GEER_FLAG_NO_GRAPH_CAPTURE | GEER_FLAG_PENG_ELL))
         return fail(GEER_E_INVALID_ARG, "unknown flags");
     if (p.schedule == GEER_SCHEDULE_LEARNED && !p.model)
