@@ -303,7 +303,8 @@ geer_status geer_autotune(geer_graph *g, int64_t nq, const int32_t *s, const int
 /* One record per kernel kind: launches, summed event-timed duration, and
  * the algorithmic bytes the launches had to move (SpMM hops: row offsets,
  * column indices, the gathered vector rows once, the written rows once and
- * the inverse degrees of the rows covered; walks: 20 bytes per step). */
+ * the inverse degrees of the rows covered; walks: one walk record per step
+ * plus the pair's two vector values on steps that read them). */
 typedef struct geer_kernel_profile {
     char name[32];
     int64_t launches;
