@@ -22,6 +22,8 @@ template <> struct Val2<double> { using type = double2; };
 // s gives the same value as the random read of the buffer.
 constexpr int32_t kMemberRowMax = 256;
 
+constexpr int kWalkBlocksPerCu = 7;
+
 __device__ __forceinline__ bool one_hop_from_graph(int32_t lb, int32_t ds, int32_t dt)
 {
     return lb == 1 && ds <= kMemberRowMax && dt <= kMemberRowMax;
@@ -350,7 +352,10 @@ geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hip
     const int rounds = (int)std::min<int64_t>(host[2], c.tau);
     if (bound == 0 || rounds <= 0) return GEER_OK;
     GEER_TRY(ws.zpart.reserve((size_t)bound * sizeof(double2)));
-    int blocks = (int)std::min<int64_t>((bound + 3) / 4, (int64_t)g->num_cus * 16);
+    // a CU holds 8 walk workgroups (32 VGPRs, 17 KB of LDS, 4 waves each);
+    // the grid fills 7 of them, so the next group's SMM kernels, queued on the
+    // other stream, always find room beside the walks
+    int blocks = (int)std::min<int64_t>((bound + 3) / 4, (int64_t)g->num_cus * kWalkBlocksPerCu);
     if (blocks >= kXcds) blocks -= blocks % kXcds;  // whole rounds over the XCDs
     const uint32_t key0 = (uint32_t)c.seed, key1 = (uint32_t)(c.seed >> 32);
     const void *rec = g->d_walk_rec;

@@ -147,7 +147,7 @@ struct geer_graph {
     // AMC phases run on stream2 while the next group's SMM runs on the query
     // stream; the events order the two slot sets between them
     hipStream_t stream2 = nullptr;
-    hipEvent_t ev_smm[2] = {nullptr, nullptr}, ev_clean[2] = {nullptr, nullptr}, ev_done = nullptr;
+    hipEvent_t ev_smm[2] = {nullptr, nullptr}, ev_clean[2] = {nullptr, nullptr};
     int num_cus = 0;
     // CSR on device
     int32_t *d_row_ptr = nullptr;

@@ -346,7 +346,6 @@ geer_status geer_graph_create(int32_t n, const int32_t *row_ptr, const int32_t *
     for (int i = 0; i < 2 && ev_ok; ++i)
         ev_ok = hipEventCreateWithFlags(&g->ev_smm[i], hipEventDisableTiming) == hipSuccess &&
                 hipEventCreateWithFlags(&g->ev_clean[i], hipEventDisableTiming) == hipSuccess;
-    ev_ok = ev_ok && hipEventCreateWithFlags(&g->ev_done, hipEventDisableTiming) == hipSuccess;
     if (!ev_ok) {
         geer_graph_destroy(g);
         return fail(GEER_E_DEVICE, "stream or event creation failed");
@@ -387,7 +386,6 @@ void geer_graph_destroy(geer_graph *g)
         if (g->ev_smm[i]) (void)hipEventDestroy(g->ev_smm[i]);
         if (g->ev_clean[i]) (void)hipEventDestroy(g->ev_clean[i]);
     }
-    if (g->ev_done) (void)hipEventDestroy(g->ev_done);
     if (g->stream2) (void)hipStreamDestroy(g->stream2);
     if (g->stream) (void)hipStreamDestroy(g->stream);
     delete g;

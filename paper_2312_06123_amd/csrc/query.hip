@@ -461,7 +461,8 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
             GEER_TRY(launch_learned(g, c, p.model, g->ws.feat.as<float>(), c.tau, c.stream));
         }
         // depths are known: bucket pairs of equal SMM depth into the same
-        // batches so that dense hops run on full batches
+        // batches so that dense hops run on full batches, shallowest first
+        // (the first group needs hop 1 only, so walks start at once)
         std::vector<int32_t> ellh(c.nq), act(c.nq), fb(c.nq);
         GEER_HIP(hipMemcpyAsync(target.data(), c.qs.lb_target, c.nq * sizeof(int32_t),
                                 hipMemcpyDeviceToHost, c.stream));
@@ -472,7 +473,7 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
         for (int64_t i = 0; i < c.nq; ++i) target[i] = act[i] ? std::min(target[i], ellh[i]) : 0;
         std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
             if (fb[a] != fb[b]) return fb[a] < fb[b];  // fallback pairs last
-            return target[a] > target[b];
+            return target[a] < target[b];
         });
         n_static = 0;
         while (n_static < c.nq && !fb[ord[n_static]]) ++n_static;
@@ -496,10 +497,13 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
             jb.gp.pend = pe;
             jb.gp.B = B;
             jb.is_static = is_static;
-            jb.set = (int)(jobs.size() % sets);
             jobs.push_back(jb);
         }
+        // the deepest group (the longest SMM, the fewest walks) goes second,
+        // where its SMM runs beside the walks of the shallowest group
+        if (is_static && jobs.size() >= 3) std::rotate(jobs.begin() + 1, jobs.end() - 1, jobs.end());
     }
+    for (size_t i = 0; i < jobs.size(); ++i) jobs[i].set = (int)(i % sets);
     const size_t set_vals = (size_t)G * 3 * g->n * kCols, set_words = (size_t)G * 3 * g->n * kBitWords;
     auto view = [&](int set) {
         SlotView v{g->ws.pool.as<char>() + set * set_vals * vs, g->ws.bits.as<uint32_t>() + set * set_words,
@@ -511,37 +515,44 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
     hipStream_t sA = c.stream, sB = sets == 2 ? g->stream2 : c.stream;
     QueryCtx cB = c;
     cB.stream = sB;
-    // AMC phase and buffer cleanup of job i (on sB, after its SMM on sA)
-    auto amc = [&](size_t i) -> geer_status {
+    // restore job i's slots to zero on sA once its walks (on sB) are done, so
+    // that the cleanup runs beside the next job's walks instead of before them
+    auto cleanup = [&](size_t i) -> geer_status {
         const Job &jb = jobs[i];
         const SlotView v = view(jb.set);
         const SlotMeta m = meta(jb.set);
+        if (sB != sA) GEER_HIP(hipStreamWaitEvent(sA, g->ev_clean[jb.set], 0));
+        return cleanup_group(g, c, v, m, slot_args(g, v, m, jb.gp), (int)jb.gp.nbat, recs[jb.set]);
+    };
+    // AMC phase of job i on sB, after its SMM on sA
+    auto amc = [&](size_t i) -> geer_status {
+        const Job &jb = jobs[i];
         if (sB != sA) GEER_HIP(hipStreamWaitEvent(sB, g->ev_smm[jb.set], 0));
         AmcGroup grp;
         grp.q0 = jb.gp.p0;
         grp.nq = std::min<int64_t>(jb.gp.pend, jb.gp.p0 + jb.gp.nbat * B) - grp.q0;
-        grp.pool = v.pool;
+        grp.pool = view(jb.set).pool;
         grp.value_size = vs;
         GEER_TRY(amc_phase(g, cB, grp, sB, p.walk_ilp));
-        GEER_TRY(cleanup_group(g, cB, v, m, slot_args(g, v, m, jb.gp), (int)jb.gp.nbat, recs[jb.set]));
-        if (sB != sA) GEER_HIP(hipEventRecord(g->ev_clean[jb.set], sB));
+        if (sB == sA) return cleanup(i);  // one stream: the next job may reuse the slots
+        GEER_HIP(hipEventRecord(g->ev_clean[jb.set], sB));
         return GEER_OK;
     };
     // the AMC phase of job i - 1 is queued (its chunk bound read first) before
-    // the SMM of job i, so both run at once on the two slot sets
+    // the SMM of job i, so both run at once on the two slot sets; job i - 2's
+    // cleanup (same slot set as job i, whose records it reads) comes first
     for (size_t i = 0; i <= jobs.size(); ++i) {
         if (i >= 1) GEER_TRY(amc(i - 1));
         if (i == jobs.size()) break;
         const Job &jb = jobs[i];
-        if (sets == 2 && i >= 2) GEER_HIP(hipStreamWaitEvent(sA, g->ev_clean[jb.set], 0));
+        if (sets == 2 && i >= 2) GEER_TRY(cleanup(i - 2));
         GEER_TRY(smm_group(g, c, view(jb.set), meta(jb.set), jb.gp, jb.is_static, target.data(), h_s,
                            h_t, ord.data(), col_tile, max_hops, recs[jb.set]));
         if (sets == 2) GEER_HIP(hipEventRecord(g->ev_smm[jb.set], sA));
     }
-    if (sets == 2) {
-        GEER_HIP(hipEventRecord(g->ev_done, sB));
-        GEER_HIP(hipStreamWaitEvent(sA, g->ev_done, 0));
-    }
+    // the last two jobs' cleanups also order sA after every walk on sB
+    if (sets == 2)
+        for (size_t i = jobs.size() >= 2 ? jobs.size() - 2 : 0; i < jobs.size(); ++i) GEER_TRY(cleanup(i));
     return GEER_OK;
 }
 
