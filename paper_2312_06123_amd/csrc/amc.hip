@@ -16,12 +16,6 @@ template <class T> struct Val2;
 template <> struct Val2<float> { using type = float2; };
 template <> struct Val2<double> { using type = double2; };
 
-// Largest row (of s or t) for which the one-hop vectors are evaluated from
-// the graph instead of read from the vector buffer: on N(s) the hop-1 vector
-// is 1/d(u), elsewhere 0, so membership in the (cache-resident) sorted row of
-// s gives the same value as the random read of the buffer.
-constexpr int32_t kMemberRowMax = 256;
-
 constexpr int kWalkBlocksPerCu = 7;
 
 __device__ __forceinline__ bool one_hop_from_graph(int32_t lb, int32_t ds, int32_t dt)

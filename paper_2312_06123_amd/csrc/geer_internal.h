@@ -63,6 +63,7 @@ struct QState {
     int32_t *s, *t, *ell, *lb, *lb_target, *lf, *batches, *stop, *active_smm, *active_amc,
         *fallback, *tau_q;
     int32_t *ord;  // batch position -> query index (batches take consecutive positions)
+    int32_t *h1w;  // 1 while the pair's two hop-1 columns hold scattered entries
     int64_t *eta1, *walk_pairs, *supp_sum, *vec_off;
     double *eps, *rb, *psi, *eta_star, *zsum, *z2sum, *var, *f, *rf, *r;
 };
@@ -177,6 +178,7 @@ struct geer_graph {
     std::vector<int32_t> h_row_ptr;        // host copy of the row offsets
     int64_t *d_nbr_work = nullptr;         // per node: sum of neighbour degrees
     int32_t *d_min_nbr_deg = nullptr;      // per node: smallest neighbour degree
+    int32_t *d_nbr_deg2 = nullptr;         // per node: second smallest (repeats counted; 0 if degree 1)
     double rho2 = 6.0, rhod = 1e6;         // cost ratios (learned-scheduler features)
     int tuned_col_tile = 0;                // autotuner's SpMM column tile (0: not tuned)
     double tile_ns[3] = {0, 0, 0};         // measured time of one tile launch at 32/64/128 columns
@@ -277,6 +279,12 @@ __host__ __device__ inline double bernstein_of(double nz, double var, double psi
 // Kernel launchers (defined in smm.hip / amc.hip)
 // ----------------------------------------------------------------------------
 
+// Largest row (of s or t) for which the walk kernel evaluates the one-hop
+// vectors from the graph instead of reading the vector buffer: on N(s) the
+// hop-1 vector is 1/d(u), elsewhere 0, so membership in the (LDS-resident)
+// sorted row of s gives the same value as the random read of the buffer.
+constexpr int32_t kMemberRowMax = 256;
+
 constexpr int kPushSplit = 8;       // blocks per column of the global sparse hop 2
 constexpr int kHashLoadMax = 9830;  // columns with more hop-2 work use the global path
 
@@ -342,6 +350,10 @@ struct QueryCtx {
     int64_t qid_offset;
     hipStream_t stream;
     int32_t ell_rule = 0;  // 0: Eq. (ell) per pair, 1: Eq. (old-ell)
+    // hop 1 from graph constants: its statistics and r_b term come from
+    // per-node tables, and the hop-1 vector is scattered only for the pairs
+    // that read it (walks that cannot evaluate it from LDS rows, dense hop 2)
+    bool hop1_implicit = false;
 };
 
 geer_status launch_init_queries(geer_graph *g, const QueryCtx &c, const int32_t *d_fixed,
@@ -349,6 +361,13 @@ geer_status launch_init_queries(geer_graph *g, const QueryCtx &c, const int32_t 
 // hop 1 (or, with clear, its reset) for slots [0, nslots)
 geer_status launch_hop1_group(geer_graph *g, const QueryCtx &c, const SlotArgs &sa, int nslots,
                               bool clear, hipStream_t st);
+// selective hop-1 scatter for slots [slot0, slot0 + nslots): kHop1Stopped
+// writes the pairs stopped after hop 1 whose walks read the vector,
+// kHop1Continuing the pairs that go on to a dense hop 2, kHop1Clear resets
+// every pair written by either
+enum { kHop1Stopped = 0, kHop1Continuing = 1, kHop1Clear = 2 };
+geer_status launch_hop1_select(geer_graph *g, const QueryCtx &c, const SlotArgs &sa, int slot0,
+                               int nslots, int mode, hipStream_t st);
 geer_status launch_hop_dense(geer_graph *g, const HopArgs &a, int value_size, hipStream_t st);
 // epilogue of hop `hop` (vectors in buffer `which`) for slots [0, nslots)
 geer_status launch_epilogue_group(geer_graph *g, const QueryCtx &c, const SlotArgs &sa,

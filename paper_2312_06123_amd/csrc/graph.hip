@@ -234,20 +234,29 @@ static geer_status build_graph(geer_graph *g, const int32_t *rp, const int32_t *
     g->max_deg = maxd;
     g->h_row_ptr.assign(rp, rp + n + 1);
     g->h_nbr_work.assign(n, 0);
-    std::vector<int32_t> mind(n, 0);
+    // hop-1 constants of each node u: the two smallest neighbour degrees
+    // (1/d of them are the two largest entries of P e_u) and sum_{v in N(u)} d(v)
+    std::vector<int32_t> mind(n, 0), mind2(n, 0);
     for (int32_t v = 0; v < n; ++v) {
         int64_t w = 0;
-        int32_t md = INT32_MAX;
+        int32_t md = INT32_MAX, md2 = INT32_MAX;
         for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
             const int32_t du = rp[ci[e] + 1] - rp[ci[e]];
             w += du;
-            md = std::min(md, du);
+            if (du < md) {
+                md2 = md;
+                md = du;
+            } else if (du < md2) {
+                md2 = du;
+            }
         }
         g->h_nbr_work[v] = w;
         mind[v] = md;
+        mind2[v] = md2 == INT32_MAX ? 0 : md2;
     }
     GEER_TRY(upload(&g->d_nbr_work, g->h_nbr_work.data(), (size_t)n));
     GEER_TRY(upload(&g->d_min_nbr_deg, mind.data(), (size_t)n));
+    GEER_TRY(upload(&g->d_nbr_deg2, mind2.data(), (size_t)n));
     // sparse-hop fixed point: a sum of at most max_deg terms, each <= 1, must fit 62 bits
     int bits = 0;
     while ((1ll << bits) <= (long long)maxd) ++bits;
@@ -367,7 +376,8 @@ void geer_graph_destroy(geer_graph *g)
     if (g->stream) (void)hipStreamSynchronize(g->stream);
     void *ptrs[] = {g->d_row_ptr,    g->d_col_idx,    g->d_inv_deg_f,       g->d_inv_deg_d,
                     g->d_light_rows, g->d_heavy_rows, g->d_heavy_seg_start, g->d_seg_begin,
-                    g->d_seg_end,    g->d_nbr_work,   g->d_min_nbr_deg,     g->d_walk_rec};
+                    g->d_seg_end,    g->d_nbr_work,   g->d_min_nbr_deg,     g->d_walk_rec,
+                    g->d_nbr_deg2};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     DevBuf *bufs[] = {&g->ws.pool,    &g->ws.bits,   &g->ws.part,      &g->ws.segbuf,

@@ -17,7 +17,7 @@ geer_status ensure_qstate(geer_graph *g, int64_t nq, QState *qs)
 {
     Workspace &ws = g->ws;
     const int64_t cap = std::max<int64_t>(nq, 1);
-    const size_t per = 13 * sizeof(int32_t) + 4 * sizeof(int64_t) + 10 * sizeof(double);
+    const size_t per = 14 * sizeof(int32_t) + 4 * sizeof(int64_t) + 10 * sizeof(double);
     GEER_TRY(ws.qstate.reserve((size_t)cap * per + 64));
     GEER_TRY(ws.misc.reserve((kMiscWords + 1024) * sizeof(int64_t)));
     GEER_TRY(ws.colstat.reserve(kCols * (2 * sizeof(double) + sizeof(int64_t))));
@@ -54,6 +54,7 @@ geer_status ensure_qstate(geer_graph *g, int64_t nq, QState *qs)
     take(qs->fallback, 4);
     take(qs->tau_q, 4);
     take(qs->ord, 4);
+    take(qs->h1w, 4);
     ws.nq_cap = cap;
     return GEER_OK;
 }
@@ -131,7 +132,8 @@ struct SlotView {
 // What a batch left in its slot (needed to restore the all-zero state of the
 // sparse buffers after the group's AMC phase).
 struct BatchRec {
-    bool hop1 = false;          // H1 holds scattered entries
+    bool hop1 = false;          // H1 holds scattered entries of every pair
+    bool hop1_sel = false;      // H1 may hold entries of the pairs flagged in h1w
     uint64_t hop2_sparse = 0;   // pairs whose hop-2 vectors were pushed into A
 };
 
@@ -281,6 +283,9 @@ static geer_status run_level(geer_graph *g, const QueryCtx &c, const SlotView &s
     for (int k = 0; k < nbat; ++k) {
         if (!hm[k] || sparse[k]) continue;
         const int win = hop == 2 ? 0 : (hop % 2 == 0 ? 2 : 1);
+        // a dense hop 2 gathers from H1: scatter it for the pairs going on
+        if (hop == 2 && c.hop1_implicit)
+            GEER_TRY(launch_hop1_select(g, c, sa, k, 1, kHop1Continuing, c.stream));
         HopArgs a;
         a.in = sv.buf(k, win);
         a.out = sv.buf(k, wout);
@@ -302,10 +307,11 @@ static geer_status cleanup_group(geer_graph *g, const QueryCtx &c, const SlotVie
                                  const SlotMeta &sm, const SlotArgs &sa, int nbat,
                                  const std::vector<BatchRec> &recs)
 {
-    bool h1 = false, h2 = false;
+    bool h1 = false, h1s = false, h2 = false;
     std::vector<uint64_t> words(nbat, 0);
     for (int k = 0; k < nbat; ++k) {
         h1 |= recs[k].hop1;
+        h1s |= recs[k].hop1_sel;
         // a dense hop that wrote A later makes it dirty: it is zeroed in full
         // before its next sparse use instead
         if (recs[k].hop2_sparse && !g->ws.a_dirty[sv.k0 + k]) {
@@ -314,6 +320,7 @@ static geer_status cleanup_group(geer_graph *g, const QueryCtx &c, const SlotVie
         }
     }
     if (h1) GEER_TRY(launch_hop1_group(g, c, sa, nbat, true, c.stream));
+    if (h1s) GEER_TRY(launch_hop1_select(g, c, sa, 0, nbat, kHop1Clear, c.stream));
     if (h2) {
         GEER_TRY(set_words(sm.h2(0), words.data(), words.size(), c.stream));
         GEER_TRY(launch_hop2_sparse(g, c, sa, 0, nbat, sv.vs, 2, c.stream));
@@ -350,9 +357,15 @@ static geer_status smm_group(geer_graph *g, const QueryCtx &c, const SlotView &s
             }
         if (L < 2) return GEER_OK;
         GEER_TRY(set_words(sm.level(0, 0, L), lv.data(), lv.size(), c.stream));
-        GEER_TRY(launch_hop1_group(g, c, sa, nbat, false, c.stream));
-        for (int k = 0; k < nbat; ++k) recs[k].hop1 = lv[(size_t)k * L + 1] != 0;
-        GEER_TRY(launch_epilogue_group(g, c, sa, nbat, 1, 0, sv.vs, c.stream));
+        if (c.hop1_implicit) {
+            GEER_TRY(launch_epilogue_group(g, c, sa, nbat, 1, 0, sv.vs, c.stream));
+            GEER_TRY(launch_hop1_select(g, c, sa, 0, nbat, kHop1Stopped, c.stream));
+            for (int k = 0; k < nbat; ++k) recs[k].hop1_sel = lv[(size_t)k * L + 1] != 0;
+        } else {
+            GEER_TRY(launch_hop1_group(g, c, sa, nbat, false, c.stream));
+            for (int k = 0; k < nbat; ++k) recs[k].hop1 = lv[(size_t)k * L + 1] != 0;
+            GEER_TRY(launch_epilogue_group(g, c, sa, nbat, 1, 0, sv.vs, c.stream));
+        }
         for (int h = 2; h < L; ++h) {
             bool any = false;
             for (int k = 0; k < nbat; ++k) {
@@ -368,12 +381,18 @@ static geer_status smm_group(geer_graph *g, const QueryCtx &c, const SlotView &s
     // greedy: level 1 for every batch, then one read of all masks per level
     hipLaunchKernelGGL(k_batch_mask, dim3(nbat), dim3(64), 0, c.stream, c.qs, sa);
     GEER_HIP(hipGetLastError());
-    GEER_TRY(launch_hop1_group(g, c, sa, nbat, false, c.stream));
+    if (c.hop1_implicit) {
+        GEER_TRY(launch_epilogue_group(g, c, sa, nbat, 1, 0, sv.vs, c.stream));
+        GEER_TRY(launch_hop1_select(g, c, sa, 0, nbat, kHop1Stopped, c.stream));
+    } else {
+        GEER_TRY(launch_hop1_group(g, c, sa, nbat, false, c.stream));
+        GEER_TRY(launch_epilogue_group(g, c, sa, nbat, 1, 0, sv.vs, c.stream));
+    }
     for (int k = 0; k < nbat; ++k) {
-        recs[k].hop1 = true;
+        recs[k].hop1 = !c.hop1_implicit;
+        recs[k].hop1_sel = c.hop1_implicit;
         dmask[k] = sm.active(k);
     }
-    GEER_TRY(launch_epilogue_group(g, c, sa, nbat, 1, 0, sv.vs, c.stream));
     for (int hop = 2;; ++hop) {
         GEER_HIP(hipMemcpyAsync(hm.data(), sm.active(0), nbat * sizeof(uint64_t), hipMemcpyDeviceToHost,
                                 c.stream));
@@ -435,6 +454,7 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
                                const int32_t *d_fixed, double min_eps, const int32_t *h_s,
                                const int32_t *h_t)
 {
+    c.hop1_implicit = true;
     // no pair can need more products than l of Eq. (ell) at d(s) = d(t) = 1
     const int max_hops = ell_of(1.0, 1.0, min_eps, c.lambda);
     const int vs = (p.flags & GEER_FLAG_FP64_VECTORS) ? 8 : 4;

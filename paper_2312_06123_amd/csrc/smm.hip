@@ -55,6 +55,7 @@ __global__ void k_init_queries(QState qs, int64_t nq, const int32_t *__restrict_
     qs.tau_q[q] = tau;
     qs.vec_off[q] = -1;
     qs.lb[q] = 0;
+    qs.h1w[q] = 0;
     bool bad = s < 0 || s >= n || t < 0 || t >= n || !(eps > 0.0) || isinf(eps);
     if (bad) {
         qs.ell[q] = 0;
@@ -711,14 +712,89 @@ geer_status launch_hop1_group(geer_graph *g, const QueryCtx &c, const SlotArgs &
     return GEER_OK;
 }
 
+// Selective hop-1 scatter (modes in geer_internal.h): one block per slot,
+// each wavefront takes whole pairs (both columns, then the pair's flag), so a
+// flag is never read and reset by different wavefronts.
+template <class T>
+__global__ __launch_bounds__(256) void k_hop1_select(QState qs, SlotArgs sa, int slot0, int mode,
+                                                     const int32_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ col_idx,
+                                                     const T *__restrict__ inv_deg)
+{
+    const int k = slot0 + (int)blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    T *h1 = slot_buf<T>(sa, k, 0);
+    uint32_t *h1_bits = slot_bits(sa, k, 0);
+    const int nb = slot_nb(sa, k);
+    for (int j = wave; j < nb; j += 4) {
+        const int64_t q = qs.ord[slot_q0(sa, k) + j];
+        const int32_t s = qs.s[q], t = qs.t[q];
+        bool need;
+        if (mode == kHop1Clear) {
+            need = qs.h1w[q] != 0;
+        } else if (qs.h1w[q] || qs.lb[q] != 1) {
+            need = false;
+        } else if (mode == kHop1Stopped) {
+            // the walk kernel evaluates the vector from LDS rows when both rows fit
+            const int32_t ds = row_ptr[s + 1] - row_ptr[s], dt = row_ptr[t + 1] - row_ptr[t];
+            need = !qs.active_smm[q] && (ds > kMemberRowMax || dt > kMemberRowMax);
+        } else {
+            need = qs.active_smm[q] != 0;
+        }
+        if (!need) continue;
+        for (int side = 0; side < 2; ++side) {
+            const int c = 2 * j + side;
+            const int32_t u = side ? t : s;
+            const uint32_t bit = 1u << (c & 31);
+            for (int32_t e = row_ptr[u] + lane; e < row_ptr[u + 1]; e += 64) {
+                const int32_t v = col_idx[e];
+                uint32_t *bw = h1_bits + (size_t)v * kBitWords + (c >> 5);
+                if (mode == kHop1Clear) {
+                    h1[(size_t)v * kCols + c] = T(0);
+                    atomicAnd(bw, ~bit);
+                } else {
+                    h1[(size_t)v * kCols + c] = inv_deg[v];
+                    atomicOr(bw, bit);
+                }
+            }
+        }
+        if (lane == 0) qs.h1w[q] = mode == kHop1Clear ? 0 : 1;
+    }
+}
+
+geer_status launch_hop1_select(geer_graph *g, const QueryCtx &c, const SlotArgs &sa, int slot0,
+                               int nslots, int mode, hipStream_t st)
+{
+    if (nslots <= 0) return GEER_OK;
+    int tok = prof_begin(g, st);
+    if (g->ws.value_size == 4)
+        hipLaunchKernelGGL(k_hop1_select<float>, dim3(nslots), dim3(256), 0, st, c.qs, sa, slot0,
+                           mode, g->d_row_ptr, g->d_col_idx, g->d_inv_deg_f);
+    else
+        hipLaunchKernelGGL(k_hop1_select<double>, dim3(nslots), dim3(256), 0, st, c.qs, sa, slot0,
+                           mode, g->d_row_ptr, g->d_col_idx, g->d_inv_deg_d);
+    prof_end(g, tok, PK_HOP1, 0.0, 0.0, st);
+    GEER_HIP(hipGetLastError());
+    return GEER_OK;
+}
+
 // ----------------------------------------------------------------------------
 // epilogue after a hop: r_b increment, switch rule, AMC parameters on stop
 // ----------------------------------------------------------------------------
 
+// 1/d rounded to the vector type, as the inverse-degree tables hold it
+template <class T> __device__ __forceinline__ double inv_as(int32_t d)
+{
+    return (double)(T)(1.0 / (double)d);
+}
+
 template <class T>
 __global__ void k_epilogue(QState qs, SlotArgs sa, int hop, int which,
                            const int32_t *__restrict__ row_ptr, int32_t schedule, int32_t tau,
-                           double delta)
+                           double delta, int implicit1, const int32_t *__restrict__ col_idx,
+                           const T *__restrict__ inv_deg, const int32_t *__restrict__ nbr_min,
+                           const int32_t *__restrict__ nbr_deg2,
+                           const int64_t *__restrict__ nbr_work)
 {
     const int k = blockIdx.x;  // batch (slot) within the group
     const int j = threadIdx.x;
@@ -734,8 +810,41 @@ __global__ void k_epilogue(QState qs, SlotArgs sa, int hop, int which,
     const double ids = 1.0 / (row_ptr[s + 1] - row_ptr[s]);
     const double idt = 1.0 / (row_ptr[t + 1] - row_ptr[t]);
     const size_t cs = 2 * j, ct = 2 * j + 1;
-    const double xs = (double)vec[(size_t)s * kCols + cs], xt = (double)vec[(size_t)t * kCols + cs];
-    const double ys = (double)vec[(size_t)s * kCols + ct], yt = (double)vec[(size_t)t * kCols + ct];
+    double xs, xt, ys, yt, m1s, m2s, m1t, m2t;
+    int64_t sd;
+    if (hop == 1 && implicit1) {
+        // P e_s is 1/d(v) on N(s) and 0 elsewhere (no self-loops): it is 0 at
+        // s, 1/d(t) at t when (s,t) is an edge; its two largest entries are
+        // 1/d of the two smallest neighbour degrees; its support N(s) has
+        // degree sum sum_{v in N(s)} d(v).  Same for t.
+        int32_t lo = row_ptr[s], hi = row_ptr[s + 1];
+        const int32_t end = hi;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (col_idx[mid] < t) lo = mid + 1;
+            else hi = mid;
+        }
+        const bool edge = lo < end && col_idx[lo] == t;
+        xs = 0.0;
+        yt = 0.0;
+        xt = edge ? (double)inv_deg[t] : 0.0;
+        ys = edge ? (double)inv_deg[s] : 0.0;
+        m1s = inv_as<T>(nbr_min[s]);
+        m2s = nbr_deg2[s] > 0 ? inv_as<T>(nbr_deg2[s]) : 0.0;
+        m1t = inv_as<T>(nbr_min[t]);
+        m2t = nbr_deg2[t] > 0 ? inv_as<T>(nbr_deg2[t]) : 0.0;
+        sd = nbr_work[s] + nbr_work[t];
+    } else {
+        xs = (double)vec[(size_t)s * kCols + cs];
+        xt = (double)vec[(size_t)t * kCols + cs];
+        ys = (double)vec[(size_t)s * kCols + ct];
+        yt = (double)vec[(size_t)t * kCols + ct];
+        m1s = cs_m1[cs];
+        m2s = cs_m2[cs];
+        m1t = cs_m1[ct];
+        m2t = cs_m2[ct];
+        sd = cs_sd[cs] + cs_sd[ct];
+    }
     // Algorithm 2: r_b += s*(s)/d(s) + t*(t)/d(t) - s*(t)/d(s) - t*(s)/d(t)
     const double rb = qs.rb[q] + (xs * ids + yt * idt - xt * ids - ys * idt);
     qs.rb[q] = rb;
@@ -744,10 +853,9 @@ __global__ void k_epilogue(QState qs, SlotArgs sa, int hop, int which,
     const int32_t lf = ell - hop;
     const double eps = qs.eps[q];
     tau = qs.tau_q[q];  // per-pair batch count (the learned schedule may set it)
-    const double psi = psi_of(lf, cs_m1[cs], cs_m2[cs], cs_m1[ct], cs_m2[ct], ids, idt);
+    const double psi = psi_of(lf, m1s, m2s, m1t, m2t, ids, idt);
     const double es = eta_star_of(psi, eps, tau, delta);
     const int64_t e1 = eta1_of(es, tau);
-    const int64_t sd = cs_sd[cs] + cs_sd[ct];
     bool stop = hop >= qs.lb_target[q];
     if (!stop && (schedule == GEER_SCHEDULE_GREEDY || qs.fallback[q])) {
         // Eq. (smm-amc): next-hop cost sum_{V_s} d + sum_{V_t} d versus h(l - l_b)
@@ -773,12 +881,15 @@ geer_status launch_epilogue_group(geer_graph *g, const QueryCtx &c, const SlotAr
 {
     if (nslots <= 0) return GEER_OK;
     int tok = prof_begin(g, st);
+    const int imp = c.hop1_implicit ? 1 : 0;
     if (value_size == 4)
         hipLaunchKernelGGL(k_epilogue<float>, dim3(nslots), dim3(64), 0, st, c.qs, sa, hop, which,
-                           g->d_row_ptr, c.schedule, c.tau, c.delta);
+                           g->d_row_ptr, c.schedule, c.tau, c.delta, imp, g->d_col_idx,
+                           g->d_inv_deg_f, g->d_min_nbr_deg, g->d_nbr_deg2, g->d_nbr_work);
     else
         hipLaunchKernelGGL(k_epilogue<double>, dim3(nslots), dim3(64), 0, st, c.qs, sa, hop, which,
-                           g->d_row_ptr, c.schedule, c.tau, c.delta);
+                           g->d_row_ptr, c.schedule, c.tau, c.delta, imp, g->d_col_idx,
+                           g->d_inv_deg_d, g->d_min_nbr_deg, g->d_nbr_deg2, g->d_nbr_work);
     prof_end(g, tok, PK_EPILOGUE, 0.0, 0.0, st);
     GEER_HIP(hipGetLastError());
     return GEER_OK;

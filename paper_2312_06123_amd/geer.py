@@ -245,6 +245,8 @@ def geer_query(g, s, t, eps, params: geer_params | None = None, stats: bool = Fa
     p = params if params is not None else geer_params_default()
     keep = None
     if fixed_ell_b is not None:
+        # a copy: the caller's params must not keep a pointer to `keep`
+        p = geer_params.from_buffer_copy(p)
         keep = np.ascontiguousarray(np.broadcast_to(np.asarray(fixed_ell_b, dtype=np.int32), (nq,)))
         p.fixed_ell_b = keep.ctypes.data
         p.schedule = GEER_SCHEDULE_FIXED

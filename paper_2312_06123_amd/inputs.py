@@ -287,6 +287,19 @@ def lollipop_graph(clique: int, tail: int) -> CSRGraph:
                       name=f"lollipop({clique},{tail})")
 
 
+def stochastic_block(blocks: int, size: int, p_in: float, p_out: float, seed: int) -> CSRGraph:
+    """Planted partition: ``blocks`` groups of ``size`` nodes, each node pair an
+    edge with probability ``p_in`` inside a group and ``p_out`` across
+    (dense rows with slow mixing); largest component."""
+    rng = np.random.default_rng(seed)
+    n = blocks * size
+    iu = np.triu_indices(n, 1)
+    same = (iu[0] // size) == (iu[1] // size)
+    keep = rng.random(iu[0].size) < np.where(same, p_in, p_out)
+    return from_edges(n, np.stack([iu[0][keep], iu[1][keep]], axis=1), largest_component=True,
+                      name=f"sbm({blocks}x{size},{p_in},{p_out})")
+
+
 # --------------------------------------------------------------------------
 # Query pairs
 # --------------------------------------------------------------------------

@@ -88,3 +88,15 @@ def test_shipped_scheduler_checkpoint_loads():
     m = G.Model(path=os.path.join(ROOT, "paper_2312_06123_amd", "data", "scheduler.geermlp"))
     p = m.get_params()
     assert np.all(np.isfinite(p)) and np.abs(p).max() > 0
+
+
+def test_fixed_depths_do_not_leak_into_caller_params():
+    # geer_query(..., fixed_ell_b=...) works on a copy of the parameters: the
+    # caller's object keeps its schedule and holds no pointer to the depths
+    p = G.geer_params_default(seed=5)
+    q = G.geer_params.from_buffer_copy(p)
+    with pytest.raises(G.GeerError):  # no graph: the call fails its argument check
+        G.geer_query(None, np.array([0], np.int32), np.array([1], np.int32), 0.1, p,
+                     fixed_ell_b=np.array([2], np.int32))
+    assert bytes(p) == bytes(q)
+    assert p.schedule == G.GEER_SCHEDULE_GREEDY and not p.fixed_ell_b

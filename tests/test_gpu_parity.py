@@ -349,3 +349,55 @@ def test_geer_mixed_fixed_depths_bucketed(cl_graph):
     assert np.all(np.abs(r[agree] - ro[agree]) <= 1e-5 * np.maximum(1.0, np.abs(ro[agree])))
     ex, _ = oracle.exact_cg(g.row_ptr, g.col_idx, s, t)
     assert np.mean(np.abs(r - ex) <= 0.1) >= 0.99
+
+
+def test_geer_dense_hop2_after_selective_hop1():
+    # On a dense graph the hop-2 work of a batch exceeds twice the edge count,
+    # so hop 2 runs as a dense product that reads the hop-1 vector; that vector
+    # is scattered only for the pairs going on (and for the walks that read
+    # it).  Four dense blocks (mean degree ~60) with sparse links between them
+    # keep lambda ~0.76, so l = 5..7 at eps = 0.05.  FP64: decisions and
+    # answers equal the checker's.
+    g = I.stochastic_block(4, 100, 0.5, 0.04, 105)
+    lam = oracle.lambda_dense(g.row_ptr, g.col_idx)
+    s, t = I.uniform_pairs(g.n, 150, 17)
+    lb = np.random.default_rng(18).integers(1, 4, len(s)).astype(np.int32)
+    p = G.geer_params_default(seed=41, flags=G.GEER_FLAG_FP64_VECTORS)
+    with _graph(g, lam) as gg:
+        r_f, st_f = G.geer_query(gg.handle, s, t, 0.05, p, stats=True, fixed_ell_b=lb)
+        r_g, st_g = G.geer_query(gg.handle, s, t, 0.05, p, stats=True)
+    assert (st_f["ell_b"] >= 2).sum() >= 64  # at least one full batch reaches hop 2
+    for (r, st), kw in (((r_f, st_f), {"schedule": "fixed", "fixed_lb": lb}),
+                        ((r_g, st_g), {"schedule": "greedy"})):
+        ro, sto = oracle.geer(g.row_ptr, g.col_idx, s, t, 0.05, lam, seed=41, **kw)
+        assert np.array_equal(st["ell"], sto["ell"])
+        agree = _stats_agree(st, sto)
+        assert agree.mean() >= 0.99
+        assert np.all(np.abs(r[agree] - ro[agree]) <= 1e-9 * np.maximum(1.0, np.abs(ro[agree])))
+
+
+def test_geer_hub_pairs_stopped_after_hop1(cl_graph):
+    # pairs with an endpoint of degree > 256 stopped after one product: their
+    # walks read the scattered hop-1 vectors; a call in between (other pairs,
+    # same slots) must leave no entries behind
+    g, lam = cl_graph
+    hubs = np.flatnonzero(g.degrees() > 256).astype(np.int32)
+    rng = np.random.default_rng(19)
+    n1 = 96
+    s = rng.choice(hubs, n1).astype(np.int32)
+    t = rng.integers(0, g.n, n1).astype(np.int32)
+    t[::2], s[::2] = s[::2].copy(), t[::2].copy()  # hub on either side
+    s2, t2 = I.uniform_pairs(g.n, 200, 20)
+    p = G.geer_params_default(seed=51)
+    one = np.ones(n1, np.int32)
+    with _graph(g, lam) as gg:
+        r1, st1 = G.geer_query(gg.handle, s, t, 0.1, p, stats=True, fixed_ell_b=one)
+        G.geer_query(gg.handle, s2, t2, 0.1, p, fixed_ell_b=np.full(len(s2), 2, np.int32))
+        r3, st3 = G.geer_query(gg.handle, s, t, 0.1, p, stats=True, fixed_ell_b=one)
+    assert np.array_equal(r1, r3)
+    ro, sto = oracle.geer(g.row_ptr, g.col_idx, s, t, 0.1, lam, seed=51, schedule="fixed",
+                          fixed_lb=one)
+    assert np.array_equal(st1["ell_b"], sto["ell_b"])
+    agree = _stats_agree(st1, sto)
+    assert agree.mean() >= 0.95
+    assert np.all(np.abs(r1[agree] - ro[agree]) <= 1e-5 * np.maximum(1.0, np.abs(ro[agree])))
