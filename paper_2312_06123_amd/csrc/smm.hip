@@ -712,23 +712,26 @@ geer_status launch_hop1_group(geer_graph *g, const QueryCtx &c, const SlotArgs &
     return GEER_OK;
 }
 
-// Selective hop-1 scatter (modes in geer_internal.h): one block per slot,
-// each wavefront takes whole pairs (both columns, then the pair's flag), so a
-// flag is never read and reset by different wavefronts.
+// Selective hop-1 scatter (modes in geer_internal.h): one block per slot.
+// Each thread tests one pair; the pairs to write (or clear) are listed in LDS
+// and each wavefront then takes whole pairs (both columns, then the pair's
+// flag), so a flag is never read and reset by different wavefronts.
 template <class T>
 __global__ __launch_bounds__(256) void k_hop1_select(QState qs, SlotArgs sa, int slot0, int mode,
                                                      const int32_t *__restrict__ row_ptr,
                                                      const int32_t *__restrict__ col_idx,
                                                      const T *__restrict__ inv_deg)
 {
+    __shared__ int32_t s_list[kMaxPairs];
+    __shared__ int32_t s_cnt;
     const int k = slot0 + (int)blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    T *h1 = slot_buf<T>(sa, k, 0);
-    uint32_t *h1_bits = slot_bits(sa, k, 0);
     const int nb = slot_nb(sa, k);
-    for (int j = wave; j < nb; j += 4) {
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    if ((int)threadIdx.x < nb) {
+        const int j = threadIdx.x;
         const int64_t q = qs.ord[slot_q0(sa, k) + j];
-        const int32_t s = qs.s[q], t = qs.t[q];
         bool need;
         if (mode == kHop1Clear) {
             need = qs.h1w[q] != 0;
@@ -736,12 +739,22 @@ __global__ __launch_bounds__(256) void k_hop1_select(QState qs, SlotArgs sa, int
             need = false;
         } else if (mode == kHop1Stopped) {
             // the walk kernel evaluates the vector from LDS rows when both rows fit
+            const int32_t s = qs.s[q], t = qs.t[q];
             const int32_t ds = row_ptr[s + 1] - row_ptr[s], dt = row_ptr[t + 1] - row_ptr[t];
             need = !qs.active_smm[q] && (ds > kMemberRowMax || dt > kMemberRowMax);
         } else {
             need = qs.active_smm[q] != 0;
         }
-        if (!need) continue;
+        if (need) s_list[atomicAdd(&s_cnt, 1)] = j;
+    }
+    __syncthreads();
+    const int cnt = s_cnt;
+    T *h1 = slot_buf<T>(sa, k, 0);
+    uint32_t *h1_bits = slot_bits(sa, k, 0);
+    for (int i = wave; i < cnt; i += 4) {
+        const int j = s_list[i];
+        const int64_t q = qs.ord[slot_q0(sa, k) + j];
+        const int32_t s = qs.s[q], t = qs.t[q];
         for (int side = 0; side < 2; ++side) {
             const int c = 2 * j + side;
             const int32_t u = side ? t : s;
