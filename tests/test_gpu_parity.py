@@ -401,3 +401,22 @@ def test_geer_hub_pairs_stopped_after_hop1(cl_graph):
     agree = _stats_agree(st1, sto)
     assert agree.mean() >= 0.95
     assert np.all(np.abs(r1[agree] - ro[agree]) <= 1e-5 * np.maximum(1.0, np.abs(ro[agree])))
+
+
+def test_geer_static_groups_any_grouping_identical(cl_graph):
+    # fixed per-pair depths: however batches are grouped and ordered into
+    # groups (group sizes 1..16 exercise the balanced group order), every
+    # result and schedule is identical
+    g, lam = cl_graph
+    s, t = I.uniform_pairs(g.n, 900, 21)
+    lb = np.random.default_rng(22).integers(0, 4, len(s)).astype(np.int32)
+    outs = []
+    with _graph(g, lam) as gg:
+        for grp in (16, 1, 2, 3):
+            p = G.geer_params_default(seed=61, group_batches=grp)
+            outs.append(G.geer_query(gg.handle, s, t, 0.1, p, stats=True, fixed_ell_b=lb))
+    r0, st0 = outs[0]
+    for r, st in outs[1:]:
+        assert np.array_equal(r, r0)
+        for f in ("ell_b", "tau", "eta1", "batches_run", "walk_pairs", "supp_sum"):
+            assert np.array_equal(st[f], st0[f]), f
