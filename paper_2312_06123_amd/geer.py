@@ -270,6 +270,8 @@ def geer_query_device(g, s, t, eps, r_out, params: geer_params | None = None, st
             raise ValueError(f"{name} must be a contiguous {dt} GPU tensor of {nq} elements")
     p = params if params is not None else geer_params_default()
     if not p.stream:
+        # a copy: the caller's params keep "no stream" (torch's current one at each call)
+        p = geer_params.from_buffer_copy(p)
         p.stream = torch.cuda.current_stream().cuda_stream
     sp = None
     if stats_out is not None:
