@@ -1,9 +1,11 @@
 // Graph residency: validation of the canonical CSR, upload to HBM, inverse
 // degrees, and the SpMM work decomposition (light rows / heavy-row segments).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 #include "geer_internal.h"
 
@@ -143,6 +145,25 @@ void prof_end_counted(geer_graph *g, int token, int kind, int counter, double pe
 
 using namespace geer;
 
+// Host threads for the O(nnz) passes over the graph (canonical-form and
+// connectivity checks, per-node tables): each reads random rows, so they are
+// bound by memory latency and scale with threads.
+static int host_threads()
+{
+    const unsigned hc = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(16u, hc ? hc : 1u));
+}
+
+// Run f(lo, hi) over [0, n) split into `parts` contiguous ranges, one thread each.
+template <class F> static void parallel_ranges(int64_t n, int parts, F f)
+{
+    parts = (int)std::max<int64_t>(1, std::min<int64_t>(parts, n));
+    std::vector<std::thread> th;
+    for (int i = 1; i < parts; ++i) th.emplace_back(f, n * i / parts, n * (i + 1) / parts);
+    f(0, n / parts);
+    for (auto &t : th) t.join();
+}
+
 static geer_status validate_csr(int32_t n, const int32_t *rp, const int32_t *ci)
 {
     if (rp[0] != 0) return fail(GEER_E_GRAPH, "row_ptr[0] must be 0");
@@ -151,39 +172,78 @@ static geer_status validate_csr(int32_t n, const int32_t *rp, const int32_t *ci)
         if (rp[v + 1] == rp[v])
             return fail(GEER_E_GRAPH, "node " + std::to_string(v) + " has degree 0");
     }
-    for (int32_t v = 0; v < n; ++v) {
-        for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
-            int32_t u = ci[e];
-            if (u < 0 || u >= n) return fail(GEER_E_GRAPH, "col_idx out of range");
-            if (u == v) return fail(GEER_E_GRAPH, "self-loop at node " + std::to_string(v));
-            if (e > rp[v] && ci[e - 1] >= u)
-                return fail(GEER_E_GRAPH, "row " + std::to_string(v) +
-                                              " not strictly ascending (unsorted or duplicate)");
-            if (!std::binary_search(ci + rp[u], ci + rp[u + 1], v))
-                return fail(GEER_E_GRAPH, "graph is not symmetric (" + std::to_string(v) + "," +
-                                              std::to_string(u) + ")");
-        }
-    }
-    // connectivity: breadth-first search from node 0
-    std::vector<int32_t> queue;
-    queue.reserve(n);
-    std::vector<char> seen(n, 0);
-    queue.push_back(0);
-    seen[0] = 1;
-    for (size_t h = 0; h < queue.size(); ++h) {
-        int32_t u = queue[h];
-        for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
-            int32_t w = ci[e];
-            if (!seen[w]) {
-                seen[w] = 1;
-                queue.push_back(w);
+    // canonical form per row (range, no self-loop, strictly ascending,
+    // symmetric); the lowest failing row is reported
+    const int T = host_threads();
+    std::vector<int32_t> bad_row(T, n);
+    std::vector<int> bad_kind(T, 0);
+    std::vector<int32_t> bad_col(T, 0);
+    std::atomic<int> part{0};
+    parallel_ranges(n, T, [&](int64_t lo, int64_t hi) {
+        const int me = part.fetch_add(1);
+        for (int32_t v = (int32_t)lo; v < (int32_t)hi; ++v) {
+            for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+                const int32_t u = ci[e];
+                int kind = 0;
+                if (u < 0 || u >= n) kind = 1;
+                else if (u == v) kind = 2;
+                else if (e > rp[v] && ci[e - 1] >= u) kind = 3;
+                else if (!std::binary_search(ci + rp[u], ci + rp[u + 1], v)) kind = 4;
+                if (kind) {
+                    bad_row[me] = v;
+                    bad_kind[me] = kind;
+                    bad_col[me] = u;
+                    return;
+                }
             }
         }
+    });
+    int w = 0;
+    for (int i = 1; i < T; ++i)
+        if (bad_row[i] < bad_row[w]) w = i;
+    if (bad_row[w] < n) {
+        const int32_t v = bad_row[w], u = bad_col[w];
+        switch (bad_kind[w]) {
+        case 1: return fail(GEER_E_GRAPH, "col_idx out of range");
+        case 2: return fail(GEER_E_GRAPH, "self-loop at node " + std::to_string(v));
+        case 3:
+            return fail(GEER_E_GRAPH, "row " + std::to_string(v) +
+                                          " not strictly ascending (unsorted or duplicate)");
+        default:
+            return fail(GEER_E_GRAPH, "graph is not symmetric (" + std::to_string(v) + "," +
+                                          std::to_string(u) + ")");
+        }
     }
-    if ((int32_t)queue.size() != n)
-        return fail(GEER_E_NOT_CONNECTED, "graph is not connected (" +
-                                              std::to_string(queue.size()) + " of " +
-                                              std::to_string(n) + " nodes reachable from 0)");
+    // connectivity: level-synchronous breadth-first search from node 0, the
+    // frontier split over threads, nodes claimed with an atomic flag
+    std::vector<std::atomic<uint8_t>> seen(n);
+    for (auto &f : seen) f.store(0, std::memory_order_relaxed);
+    std::vector<int32_t> frontier{0};
+    seen[0].store(1, std::memory_order_relaxed);
+    int64_t reached = 1;
+    while (!frontier.empty()) {
+        std::vector<std::vector<int32_t>> next(T);
+        std::atomic<int> slot{0};
+        parallel_ranges((int64_t)frontier.size(), T, [&](int64_t lo, int64_t hi) {
+            std::vector<int32_t> &out = next[slot.fetch_add(1)];
+            for (int64_t h = lo; h < hi; ++h) {
+                const int32_t u = frontier[h];
+                for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+                    const int32_t x = ci[e];
+                    if (!seen[x].load(std::memory_order_relaxed) &&
+                        !seen[x].exchange(1, std::memory_order_relaxed))
+                        out.push_back(x);
+                }
+            }
+        });
+        frontier.clear();
+        for (auto &v : next) frontier.insert(frontier.end(), v.begin(), v.end());
+        reached += (int64_t)frontier.size();
+    }
+    if (reached != n)
+        return fail(GEER_E_NOT_CONNECTED, "graph is not connected (" + std::to_string(reached) +
+                                              " of " + std::to_string(n) +
+                                              " nodes reachable from 0)");
     return GEER_OK;
 }
 
@@ -237,23 +297,25 @@ static geer_status build_graph(geer_graph *g, const int32_t *rp, const int32_t *
     // hop-1 constants of each node u: the two smallest neighbour degrees
     // (1/d of them are the two largest entries of P e_u) and sum_{v in N(u)} d(v)
     std::vector<int32_t> mind(n, 0), mind2(n, 0);
-    for (int32_t v = 0; v < n; ++v) {
-        int64_t w = 0;
-        int32_t md = INT32_MAX, md2 = INT32_MAX;
-        for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
-            const int32_t du = rp[ci[e] + 1] - rp[ci[e]];
-            w += du;
-            if (du < md) {
-                md2 = md;
-                md = du;
-            } else if (du < md2) {
-                md2 = du;
+    parallel_ranges(n, host_threads(), [&](int64_t lo, int64_t hi) {
+        for (int32_t v = (int32_t)lo; v < (int32_t)hi; ++v) {
+            int64_t w = 0;
+            int32_t md = INT32_MAX, md2 = INT32_MAX;
+            for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+                const int32_t du = rp[ci[e] + 1] - rp[ci[e]];
+                w += du;
+                if (du < md) {
+                    md2 = md;
+                    md = du;
+                } else if (du < md2) {
+                    md2 = du;
+                }
             }
+            g->h_nbr_work[v] = w;
+            mind[v] = md;
+            mind2[v] = md2 == INT32_MAX ? 0 : md2;
         }
-        g->h_nbr_work[v] = w;
-        mind[v] = md;
-        mind2[v] = md2 == INT32_MAX ? 0 : md2;
-    }
+    });
     GEER_TRY(upload(&g->d_nbr_work, g->h_nbr_work.data(), (size_t)n));
     GEER_TRY(upload(&g->d_min_nbr_deg, mind.data(), (size_t)n));
     GEER_TRY(upload(&g->d_nbr_deg2, mind2.data(), (size_t)n));

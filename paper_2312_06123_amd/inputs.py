@@ -207,7 +207,8 @@ def chung_lu(n: int, gamma: float, mean_degree: float, seed: int) -> CSRGraph:
                       name=f"chung_lu(n={n},gamma={gamma},deg={mean_degree},seed={seed})")
 
 
-def rmat(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int) -> CSRGraph:
+def rmat(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int,
+         progress=None) -> CSRGraph:
     """R-MAT graph with 2^scale nodes and edge_factor * 2^scale edge samples.
 
     Each sample descends ``scale`` levels of the adjacency matrix, choosing a
@@ -217,6 +218,8 @@ def rmat(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int) 
     not depend on the thread count).  Node labels are then permuted by a seeded
     permutation (removing the generator's id locality), the result is
     symmetrised and deduplicated, and the largest component is kept.
+    ``progress``, if given, is called with a short message after every 16
+    chunks and before the CSR is built.
     """
     from concurrent.futures import ThreadPoolExecutor
 
@@ -246,7 +249,11 @@ def rmat(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int) 
         out[lo:lo + cnt, 1] = perm[dst]
 
     with ThreadPoolExecutor(max_workers=max(1, min(8, os.cpu_count() or 1))) as ex:
-        list(ex.map(draw, range(nchunks)))
+        for i, _ in enumerate(ex.map(draw, range(nchunks))):
+            if progress and ((i + 1) % 16 == 0 or i + 1 == nchunks):
+                progress(f"rmat: {i + 1}/{nchunks} sample chunks")
+    if progress:
+        progress("rmat: building the CSR")
     return from_edges(n, out, largest_component=True,
                       name=f"rmat(scale={scale},ef={edge_factor},seed={seed})")
 

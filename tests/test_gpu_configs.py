@@ -11,7 +11,13 @@
   * the learned checkpoint on a fresh Chung-Lu graph (n = 2 * 10^6, the 1M
     configuration's parameters), 50,000 uniform pairs, eps = 0.05: the model
     applies to most pairs, sampled answers are within eps of the exact
-    resistance and equal the checker's run at the same (l_b, tau).
+    resistance and equal the checker's run at the same (l_b, tau);
+  * R-MAT scale 24 (16 * 2^24 samples, ~5 * 10^8 CSR entries, fully resident),
+    10^6 degree-proportional pairs, eps = 0.02, learned schedule, run in
+    chunks of 10^5 pairs (walk ids continue across chunks): sampled answers
+    replayed by the checker and checked against the exact resistance.  Only
+    with GEER_TEST_RMAT24=1: generating the graph alone takes minutes of host
+    time and ~35 GB of host memory.
 """
 
 import os
@@ -140,3 +146,71 @@ def test_cl2m_learned_replay(cl2m_run):
     same = (sto["eta1"] == st["eta1"][sample]) & (sto["batches_run"] == st["batches_run"][sample])
     assert same.mean() >= 0.9
     assert np.all(np.abs(r[sample][same] - ro[same]) <= 1e-5 * np.maximum(1.0, np.abs(ro[same])))
+
+
+# ---------------------------------------------------------------------------
+# R-MAT scale 24, 10^6 degree-proportional pairs, eps = 0.02 (opt-in)
+# ---------------------------------------------------------------------------
+
+RMAT24 = os.environ.get("GEER_TEST_RMAT24") == "1"
+rmat24_only = pytest.mark.skipif(not RMAT24, reason="R-MAT scale 24 generation takes minutes of host "
+                                 "time; set GEER_TEST_RMAT24=1")
+
+
+@pytest.fixture(scope="module")
+def rmat24_run():
+    import time
+
+    t0 = time.time()
+    g = I.rmat(24, 16, 0.57, 0.19, 0.19, 1005, progress=lambda m: print(f"[rmat24] {m}", flush=True))
+    print(f"[rmat24] graph n={g.n} nnz={g.nnz} d_max={int(g.degrees().max())} "
+          f"in {time.time() - t0:.0f} s", flush=True)
+    nq, chunk, budget_s = 1_000_000, 100_000, 300.0
+    s, t = I.degree_pairs(g, nq, 2005)
+    r = np.full(nq, np.nan)
+    st = None
+    done, busy = 0, 0.0
+    with G.Graph(g.n, g.row_ptr32(), g.col_idx) as gg:
+        print(f"[rmat24] graph on the GPU after {time.time() - t0:.0f} s", flush=True)
+        lam = G.geer_graph_compute_lambda(gg.handle, 400, 1e-8, 7)
+        print(f"[rmat24] lambda={lam:.6f} after {time.time() - t0:.0f} s", flush=True)
+        ts, tt = I.uniform_pairs(g.n, 1024, 2105)
+        G.geer_autotune(gg.handle, ts, tt, 0.02)
+        print(f"[rmat24] autotuned after {time.time() - t0:.0f} s", flush=True)
+        model = G.Model(path=os.path.join(ROOT, "paper_2312_06123_amd", "data", "scheduler.geermlp"))
+        while done < nq and busy < budget_s:
+            hi = min(nq, done + chunk)
+            p = G.geer_params_default(seed=3005, schedule=G.GEER_SCHEDULE_LEARNED,
+                                      model=model.handle.value, qid_offset=done)
+            c0 = time.time()
+            rc, stc = G.geer_query(gg.handle, s[done:hi], t[done:hi], 0.02, p, stats=True)
+            busy += time.time() - c0
+            r[done:hi] = rc
+            st = stc if st is None else np.concatenate([st, stc])
+            done = hi
+            print(f"[rmat24] {done} pairs in {busy:.1f} s ({done / busy:.0f} pairs/s)", flush=True)
+    sample = np.random.default_rng(5).choice(np.arange(done), 8, replace=False)
+    return g, s, t, lam, r, st, done, sample
+
+
+@pytest.mark.gpu
+@rmat24_only
+def test_rmat24_learned_replay(rmat24_run):
+    g, s, t, lam, r, st, done, sample = rmat24_run
+    assert np.all(np.isfinite(r[:done]))
+    ro, sto = oracle.geer(g.row_ptr, g.col_idx, s[sample], t[sample], 0.02, lam, seed=3005,
+                          schedule="fixed", fixed_lb=st["ell_b"][sample], qid=sample,
+                          tau_per_pair=st["tau"][sample])
+    assert np.array_equal(sto["ell"], st["ell"][sample])
+    same = (sto["eta1"] == st["eta1"][sample]) & (sto["batches_run"] == st["batches_run"][sample])
+    assert same.mean() >= 0.75
+    got = r[sample][same]
+    assert np.all(np.abs(got - ro[same]) <= 1e-5 * np.maximum(1.0, np.abs(ro[same])))
+
+
+@pytest.mark.gpu
+@rmat24_only
+def test_rmat24_exact_on_sample(rmat24_run):
+    g, s, t, lam, r, st, done, sample = rmat24_run
+    ex, _ = oracle.exact_cg(g.row_ptr, g.col_idx, s[sample], t[sample], tol=1e-8)
+    assert np.all(np.abs(r[sample] - ex) <= 0.02)
