@@ -84,6 +84,7 @@ struct Workspace {
     DevBuf meta;      // per-slot masks (active, hop-2 cleanup, hop-2 paths, static levels)
     DevBuf feat;      // learned scheduler: per-pair features
     int acc_slots = 0;          // slots of all-zero accumulators held in acc
+    bool in_use = false;        // a call holds entries in the slot buffers (set until it restores them)
     std::vector<char> a_dirty;  // per slot: buffer A was written by a dense hop
     int slots = 0;
     int value_size = 0;

@@ -59,6 +59,18 @@ geer_status ensure_qstate(geer_graph *g, int64_t nq, QState *qs)
     return GEER_OK;
 }
 
+// Slot buffers and hop-2 accumulators are all zero between calls.  A call
+// that fails after filling them leaves `in_use` set; the next call then has
+// them cleared again (by ensure_slots / ensure_hop2_acc) before any use.
+static void begin_slot_use(geer_graph *g)
+{
+    if (g->ws.in_use) {
+        g->ws.slots = 0;
+        g->ws.acc_slots = 0;
+    }
+    g->ws.in_use = true;
+}
+
 geer_status ensure_slots(geer_graph *g, int slots, int value_size)
 {
     Workspace &ws = g->ws;
@@ -454,6 +466,7 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
                                const int32_t *d_fixed, double min_eps, const int32_t *h_s,
                                const int32_t *h_t)
 {
+    begin_slot_use(g);
     c.hop1_implicit = true;
     // no pair can need more products than l of Eq. (ell) at d(s) = d(t) = 1
     const int max_hops = ell_of(1.0, 1.0, min_eps, c.lambda);
@@ -573,6 +586,7 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
     // the last two jobs' cleanups also order sA after every walk on sB
     if (sets == 2)
         for (size_t i = jobs.size() >= 2 ? jobs.size() - 2 : 0; i < jobs.size(); ++i) GEER_TRY(cleanup(i));
+    g->ws.in_use = false;
     return GEER_OK;
 }
 
@@ -749,6 +763,7 @@ geer_status geer_smm(geer_graph *g, int32_t nq, const int32_t *s, const int32_t 
     c.schedule = GEER_SCHEDULE_FIXED;
     c.seed = 0;
     c.qid_offset = 0;
+    begin_slot_use(g);
     GEER_TRY(ensure_slots(g, std::max(1, g->ws.slots), vs));
     std::vector<double> ones(nq, 1.0);
     GEER_HIP(hipMemcpyAsync(c.qs.s, s, nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
@@ -832,6 +847,7 @@ geer_status geer_smm(geer_graph *g, int32_t nq, const int32_t *s, const int32_t 
         GEER_TRY(cleanup_group(g, c, sv, sm, slot_args(g, sv, sm, gp), 1, recs));
         GEER_HIP(hipStreamSynchronize(st));
     }
+    g->ws.in_use = false;
     return GEER_OK;
 }
 
@@ -945,9 +961,9 @@ extern "C" geer_status geer_amc(geer_graph *g, int32_t s, int32_t t, const doubl
             ((double *)host.data())[2 * (size_t)v + 1] = y[v];
         }
     }
+    g->ws.a_dirty[0] = 1;  // A holds dense caller vectors (zeroed in full before a sparse use)
     GEER_HIP(hipMemcpy2D(sv.buf(0, 1), (size_t)kCols * vs, host.data(), (size_t)2 * vs, (size_t)2 * vs,
                          (size_t)n, hipMemcpyHostToDevice));
-    g->ws.a_dirty[0] = 1;  // A now holds dense caller vectors
     c.stream = st;
     const int32_t zero = 0;
     GEER_HIP(hipMemcpyAsync(c.qs.s, &s, sizeof(int32_t), hipMemcpyHostToDevice, st));

@@ -420,3 +420,23 @@ def test_geer_static_groups_any_grouping_identical(cl_graph):
         assert np.array_equal(r, r0)
         for f in ("ell_b", "tau", "eta1", "batches_run", "walk_pairs", "supp_sum"):
             assert np.array_equal(st[f], st0[f]), f
+
+
+def test_geer_failed_call_leaves_no_entries(cl_graph):
+    # A call that fails after its SMM phase (one pair would need more than
+    # 2^32 walks) must leave nothing behind in the slot buffers: the next
+    # call, on other pairs, equals the same call on a fresh graph handle.
+    g, lam = cl_graph
+    s1, t1 = I.uniform_pairs(g.n, 300, 23)
+    s2, t2 = I.uniform_pairs(g.n, 300, 24)
+    lb2 = np.full(300, 2, np.int32)
+    p = G.geer_params_default(seed=71)
+    with _graph(g, lam) as fresh:
+        r_ref = G.geer_query(fresh.handle, s2, t2, 0.1, p, fixed_ell_b=lb2)
+    eps = np.full(300, 0.1)
+    eps[5] = 1e-7
+    with _graph(g, lam) as gg:
+        with pytest.raises(G.GeerError):
+            G.geer_query(gg.handle, s1, t1, eps, p, fixed_ell_b=lb2)
+        r = G.geer_query(gg.handle, s2, t2, 0.1, p, fixed_ell_b=lb2)
+    assert np.array_equal(r, r_ref)
