@@ -11,12 +11,16 @@ one by one:
     per-pair schedule (l_b, tau) wherever the FP32 and FP64 runs take the
     same walk-count decisions (relative 1e-5);
   * GPU lambda (Lanczos, widened by residuals) sits on or just above ARPACK's;
+  * gain of the learned schedule: fewer walk steps and SMM products than the
+    greedy switch of the plain method, and at least 1.2x its pairs/s (second,
+    warm call of each, same pairs);
   * coverage (Definition 2.2): on 1,000 further pairs drawn without replacement,
     the fraction with |r' - r| > eps is consistent with the failure
     probability delta = 0.01, judged by the Clopper-Pearson 95% interval.
 """
 
 import os
+import time
 
 import numpy as np
 import pytest
@@ -28,6 +32,7 @@ G = pytest.importorskip("paper_2312_06123_amd.geer")
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 EPS = 0.05
 DELTA = 0.01  # the default failure probability
+WARM_SECONDS = {}  # wall time of a second call of each schedule (filled by the fixture)
 
 
 @pytest.fixture(scope="module")
@@ -43,8 +48,14 @@ def bench_run():
                                    model=model.handle.value)
         r_l, st_l = G.geer_query(gg.handle, s, t, EPS, pl, stats=True)
         r_p, st_p = G.geer_query(gg.handle, s, t, EPS, G.geer_params_default(seed=3002), stats=True)
+        secs = {}
+        for name, p in (("learned", pl), ("plain", G.geer_params_default(seed=3002))):
+            t0 = time.perf_counter()
+            G.geer_query(gg.handle, s, t, EPS, p)
+            secs[name] = time.perf_counter() - t0
     rng = np.random.default_rng(0)
     sample = np.concatenate([np.arange(24), rng.choice(np.arange(24, len(s)), 24, replace=False)])
+    WARM_SECONDS.update(secs)
     return g, s, t, lam, r_l, st_l, r_p, st_p, sample
 
 
@@ -90,6 +101,22 @@ def test_fullsize_plain_replay(bench_run):
     assert same.mean() >= 0.9
     got = r_p[sample][same]
     assert np.all(np.abs(got - ro[same]) <= 1e-5 * np.maximum(1.0, np.abs(ro[same])))
+
+
+@pytest.mark.gpu
+def test_fullsize_learned_gain(bench_run):
+    g, s, t, lam, r_l, st_l, r_p, st_p, sample = bench_run
+    secs = WARM_SECONDS
+
+    def steps(st):
+        return int((2 * st["walk_pairs"] * (st["ell"] - st["ell_b"])).sum())
+
+    print(f"learned: {steps(st_l)} walk steps, {int(st_l['ell_b'].sum())} products, "
+          f"{len(s) / secs['learned']:.0f} pairs/s; plain: {steps(st_p)} walk steps, "
+          f"{int(st_p['ell_b'].sum())} products, {len(s) / secs['plain']:.0f} pairs/s", flush=True)
+    assert steps(st_l) < steps(st_p)
+    assert st_l["ell_b"].sum() < st_p["ell_b"].sum()
+    assert secs["plain"] / secs["learned"] >= 1.2
 
 
 def clopper_pearson(k: int, n: int, level: float = 0.95):
