@@ -17,6 +17,12 @@ template <> struct Val2<float> { using type = float2; };
 template <> struct Val2<double> { using type = double2; };
 
 constexpr int kWalkBlocksPerCu = 7;
+// Each round's chunks are walked by two launches (each a contiguous half,
+// split over the XCDs).  The other stream's kernels start mostly while a walk
+// launch drains, so a second drain point per round lets the next group's SMM
+// advance; on the 1M-node Chung-Lu workload 1, 2, 3 and 4 parts gave 219-221K,
+// 221.8-222.8K, 220.8K and 219.3K pairs/s.
+constexpr int kWalkParts = 2;
 
 __device__ __forceinline__ bool one_hop_from_graph(int32_t lb, int32_t ds, int32_t dt)
 {
@@ -174,7 +180,7 @@ __global__ __launch_bounds__(256) void k_walk(QState qs, int64_t q0, int nq, int
                                               const void *__restrict__ rec, uint32_t rec_sb,
                                               uint32_t rec_sd, const T *__restrict__ pool,
                                               uint32_t key0, uint32_t key1, int64_t qid_offset,
-                                              double2 *__restrict__ zpart)
+                                              double2 *__restrict__ zpart, int part, int nparts)
 {
     using T2 = typename Val2<T>::type;
     // chunk offsets in LDS as 32-bit values when they fit
@@ -194,7 +200,9 @@ __global__ __launch_bounds__(256) void k_walk(QState qs, int64_t q0, int nq, int
     // walks revisit belong to few slots and can stay in that XCD's L2.
     const int nx = gridDim.x % kXcds == 0 ? kXcds : 1;
     const int xcd = blockIdx.x % nx;
-    const int64_t c_lo = total * xcd / nx, c_hi = total * (xcd + 1) / nx;
+    // this launch's part of the round's chunks, then the XCD's share of it
+    const int64_t p_lo = total * part / nparts, span = total * (part + 1) / nparts - p_lo;
+    const int64_t c_lo = p_lo + span * xcd / nx, c_hi = p_lo + span * (xcd + 1) / nx;
     const int64_t gw = (int64_t)(blockIdx.x / nx) * 4 + wv;
     const int64_t nw = (int64_t)(gridDim.x / nx) * 4;
     const uint32_t side = lane & 1;
@@ -364,24 +372,28 @@ geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hip
         hipLaunchKernelGGL(k_amc_plan, dim3(1), dim3(1024), 0, st, c.qs, grp.q0, nq, round,
                            chunk_off, d_total, d_steps, g->d_row_ptr);
         GEER_HIP(hipGetLastError());
-        int tok = prof_begin(g, st);
+        for (int part = 0; part < kWalkParts; ++part) {
+            int tok = prof_begin(g, st);
 #define GEER_WALK_LAUNCH(T, RB)                                                                 \
     hipLaunchKernelGGL((k_walk<T, RB>), dim3(blocks), dim3(256), 0, st, c.qs, grp.q0, nq, round, \
                        chunk_off, d_total, g->d_row_ptr, g->d_col_idx, rec, sb, sd,             \
-                       (const T *)grp.pool, key0, key1, c.qid_offset, zp)
-        if (grp.value_size == 4) {
-            if (g->walk_rec_bytes == 8) GEER_WALK_LAUNCH(float, 8);
-            else GEER_WALK_LAUNCH(float, 16);
-        } else {
-            if (g->walk_rec_bytes == 8) GEER_WALK_LAUNCH(double, 8);
-            else GEER_WALK_LAUNCH(double, 16);
-        }
+                       (const T *)grp.pool, key0, key1, c.qid_offset, zp, part, kWalkParts)
+            if (grp.value_size == 4) {
+                if (g->walk_rec_bytes == 8) GEER_WALK_LAUNCH(float, 8);
+                else GEER_WALK_LAUNCH(float, 16);
+            } else {
+                if (g->walk_rec_bytes == 8) GEER_WALK_LAUNCH(double, 8);
+                else GEER_WALK_LAUNCH(double, 16);
+            }
 #undef GEER_WALK_LAUNCH
-        GEER_HIP(hipGetLastError());
-        // per step: one walk record; steps of pairs whose vectors are read
-        // also fetch the pair's two values at the new node
-        prof_end_counted(g, tok, PK_WALK, counter, (double)g->walk_rec_bytes,
-                         2.0 * grp.value_size, st);
+            GEER_HIP(hipGetLastError());
+            // per step: one walk record; steps of pairs whose vectors are
+            // read also fetch the pair's two values at the new node (the
+            // round's steps are booked on its last launch)
+            if (part + 1 < kWalkParts) prof_end(g, tok, PK_WALK, 0.0, 0.0, st);
+            else prof_end_counted(g, tok, PK_WALK, counter, (double)g->walk_rec_bytes,
+                                  2.0 * grp.value_size, st);
+        }
         hipLaunchKernelGGL(k_amc_stop, dim3((nq + 3) / 4), dim3(256), 0, st, c.qs, grp.q0, nq,
                            round, chunk_off, zp, c.tau, c.delta);
         GEER_HIP(hipGetLastError());
