@@ -256,7 +256,7 @@ geer_status geer_model_set_norm(geer_model *m, const float *mean, const float *s
                                 const float *lo, const float *hi);
 /* Cost ratios used as features: rho2 = cost of one unit of hop-2 push work,
  * rhod = cost of one dense hop of a 64-pair batch divided by 64, both in
- * units of one walk step (geer_autotune measures them). */
+ * units of geer_tuning.ns_per_walk_step (geer_autotune measures them). */
 geer_status geer_graph_set_costs(geer_graph *g, double rho2, double rhod);
 /* Raw features of nq pairs: host float[nq * GEER_MLP_FEATURES]. */
 geer_status geer_features(geer_graph *g, int64_t nq, const int32_t *s, const int32_t *t,
@@ -283,7 +283,10 @@ geer_status geer_mlp_train(geer_model *m, int64_t n, const float *x, const float
 typedef struct geer_tuning {
     int32_t col_tile;          /* fastest SpMM column tile (32, 64 or 128) */
     int32_t from_cache;        /* 1 if read from the cache file */
-    double ns_per_walk_step;   /* measured cost of one walk step */
+    double ns_per_walk_step;   /* the cost unit: one walk step of a pair stopped after one
+                                  product whose rows of s and t have at most 256 entries (no
+                                  vector read); steps that read SMM vectors cost about twice
+                                  as much */
     double ns_per_hop2_unit;   /* one unit of sparse hop-2 work (one CSR entry of one column) */
     double ns_per_dense_hop;   /* one dense hop of a 64-pair batch */
     double rho2, rhod;         /* the cost ratios stored with geer_graph_set_costs */

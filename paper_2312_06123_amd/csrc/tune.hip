@@ -122,6 +122,40 @@ extern "C" geer_status geer_autotune(geer_graph *g, int64_t nq, const int32_t *s
         }
         if (tn.ns_per_walk_step >= 1e300) tn.ns_per_walk_step = 0.05;
         if (tn.ns_per_hop2_unit >= 1e300) tn.ns_per_hop2_unit = 0.3;
+        // 3. the cost unit: a walk step of a pair stopped after one product
+        // whose rows of s and t fit the walk kernel's LDS rows (the step reads
+        // one walk record and no vector).  Steps that also read the pair's
+        // vectors cost about twice as much, a difference the learned model's
+        // step counts do not see; with the cheap step as the unit of its cost
+        // ratios it picked better depths on every workload measured.
+        std::vector<int32_t> ms, mt;
+        std::vector<double> me;
+        for (int64_t i = 0; i < nq; ++i) {
+            if (s[i] < 0 || s[i] >= g->n || t[i] < 0 || t[i] >= g->n || s[i] == t[i]) continue;
+            const int32_t ds = g->h_row_ptr[s[i] + 1] - g->h_row_ptr[s[i]];
+            const int32_t dt = g->h_row_ptr[t[i] + 1] - g->h_row_ptr[t[i]];
+            if (ds > kMemberRowMax || dt > kMemberRowMax) continue;
+            ms.push_back(s[i]);
+            mt.push_back(t[i]);
+            me.push_back(eps[i]);
+        }
+        if (!ms.empty()) {
+            const int64_t nm = (int64_t)ms.size();
+            std::vector<int32_t> one(nm, 1);
+            std::vector<double> rm(nm);
+            p.schedule = GEER_SCHEDULE_FIXED;
+            p.fixed_ell_b = one.data();
+            double member = 1e300;
+            for (int rep = 0; rep < kReps; ++rep) {
+                GEER_TRY(geer_profile_enable(g, 1));
+                GEER_TRY(geer_query(g, nm, ms.data(), mt.data(), me.data(), &p, rm.data(), nullptr));
+                GEER_TRY(geer_profile_read(g, prof, 32, &cnt));
+                GEER_TRY(geer_profile_enable(g, 0));
+                const geer_kernel_profile &w = prof[PK_WALK];
+                if (w.work_units > 0) member = std::min(member, 1e6 * w.total_ms / w.work_units);
+            }
+            if (member < 1e300) tn.ns_per_walk_step = member;
+        }
         if (cache_path) {
             FILE *f = std::fopen(cache_path, "a");
             if (f) {
