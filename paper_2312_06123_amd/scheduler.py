@@ -149,8 +149,8 @@ def train_model(X, Y, W, steps=30000, seed=11, lr=2e-3):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
-    ap.add_argument("--scale", type=float, default=1.0, help="multiplies every graph's pair count")
-    ap.add_argument("--steps", type=int, default=30000)
+    ap.add_argument("--scale", type=float, default=2.0, help="multiplies every graph's pair count")
+    ap.add_argument("--steps", type=int, default=60000)
     ap.add_argument("--report", default=None)
     a = ap.parse_args(argv)
     rng = np.random.default_rng(4)
