@@ -97,15 +97,20 @@ def label(feats, runs, r_ref, rng, n_rho=4):
     return np.concatenate(Xs), np.concatenate(Ys), np.concatenate(Ws)
 
 
-def graph_runs(g, nq, n_edge, eps_choices, seed, rng):
+def graph_runs(g, nq, n_edge, n_deg, eps_choices, seed, rng):
     """Features, schedule sweep and reference answers on one training graph:
-    ``nq`` uniform pairs and ``n_edge`` pairs that are edges of the graph.
-    Each pair draws its eps from ``eps_choices``."""
+    ``nq`` uniform pairs, ``n_edge`` pairs that are edges of the graph and
+    ``n_deg`` pairs with both endpoints drawn by degree.  Each pair draws its
+    eps from ``eps_choices``."""
     s, t = I.uniform_pairs(g.n, nq, seed)
     if n_edge:
         se, te = I.edge_pairs(g, n_edge, seed + 7)
         s, t = np.concatenate([s, se]), np.concatenate([t, te])
         nq += n_edge
+    if n_deg:
+        sd, td = I.degree_pairs(g, n_deg, seed + 9)
+        s, t = np.concatenate([s, sd]), np.concatenate([t, td])
+        nq += n_deg
     eps = np.random.default_rng(seed + 1).choice(np.asarray(eps_choices, dtype=np.float64), nq)
     with G.Graph(g.n, g.row_ptr32(), g.col_idx) as gg:
         lam = G.geer_graph_compute_lambda(gg.handle, 300, 1e-9, seed)
@@ -118,19 +123,21 @@ def graph_runs(g, nq, n_edge, eps_choices, seed, rng):
     return label(feats, runs, r_ref, rng)
 
 
-# Training graphs: (generator, uniform pairs, edge pairs, eps choices, pair
-# seed).  The config-1 uniform graph alone has no degree skew and short walks;
-# the power-law and R-MAT graphs widen the features the model sees
-# (hub-dominated neighbour sums, lambda from 0.6 to 0.9, so l from a few hops
-# to ~70).  Edge pairs (the paper's second workload) add the edge feature.
+# Training graphs: (generator, uniform pairs, edge pairs, degree-drawn pairs,
+# eps choices, pair seed).  The config-1 uniform graph alone has no degree
+# skew and short walks; the power-law and R-MAT graphs widen the features the
+# model sees (hub-dominated neighbour sums, lambda from 0.6 to 0.9, so l from
+# a few hops to ~70).  Edge pairs (the paper's second workload) add the edge
+# feature, degree-drawn pairs the hub endpoints.
 def training_graphs(scale=1.0):
     def q(n):
         return max(16, int(n * scale))
     return [
-        (lambda: I.erdos_renyi_path(10_000, 10, 1001), q(4000), q(1000), (0.05,), 4001),
-        (lambda: I.chung_lu(200_000, 2.1, 20, 5004), q(3000), q(1000), (0.02, 0.05, 0.1), 4002),
-        (lambda: I.chung_lu(300_000, 2.1, 12, 5005), q(3000), q(1000), (0.02, 0.05, 0.1), 4003),
-        (lambda: I.rmat(17, 16, 0.57, 0.19, 0.19, 5006), q(2500), q(800), (0.02, 0.05, 0.1), 4004),
+        (lambda: I.erdos_renyi_path(10_000, 10, 1001), q(4000), q(1000), 0, (0.05,), 4001),
+        (lambda: I.chung_lu(200_000, 2.1, 20, 5004), q(3000), q(1000), q(750), (0.02, 0.05, 0.1), 4002),
+        (lambda: I.chung_lu(300_000, 2.1, 12, 5005), q(3000), q(1000), q(750), (0.02, 0.05, 0.1), 4003),
+        (lambda: I.rmat(17, 16, 0.57, 0.19, 0.19, 5006), q(2500), q(800), q(1000), (0.02, 0.05, 0.1),
+         4004),
     ]
 
 
@@ -156,10 +163,10 @@ def main(argv=None):
     rng = np.random.default_rng(4)
     parts = []
     runs_total = 0
-    for make, nq, n_edge, eps_choices, seed in training_graphs(a.scale):
+    for make, nq, n_edge, n_deg, eps_choices, seed in training_graphs(a.scale):
         g = make()
-        parts.append(graph_runs(g, nq, n_edge, eps_choices, seed, rng))
-        runs_total += (nq + n_edge) * len(DEPTHS) * len(TAUS)
+        parts.append(graph_runs(g, nq, n_edge, n_deg, eps_choices, seed, rng))
+        runs_total += (nq + n_edge + n_deg) * len(DEPTHS) * len(TAUS)
     X = np.concatenate([p[0] for p in parts])
     Y = np.concatenate([p[1] for p in parts])
     W = np.concatenate([p[2] for p in parts])
