@@ -221,7 +221,8 @@ geer_status geer_amc(geer_graph *g, int32_t s, int32_t t, const double *x, const
 /* A 3-layer MLP (GEER_MLP_FEATURES -> 64 -> 64 -> 3, ReLU) that predicts, per
  * pair, the SMM depth l_b, the AMC batch count tau and log10 of the absolute
  * error.  Used by GEER_SCHEDULE_LEARNED; pairs whose predicted error exceeds
- * eps or whose features leave the training range use the greedy switch of
+ * eps or whose per-pair structural features (features 0..8) leave the
+ * training range widened by a tenth of its span use the greedy switch of
  * Eq. (smm-amc).  The predicted depth is guarded by exact graph quantities: at
  * least one product when l >= 1, and two when a lower bound of the first walk
  * batch after one product exceeds the hop-2 cost (rho2 times the neighbour

@@ -349,6 +349,8 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float *__restrict__ para
 // learned schedule: features -> normalise -> BF16 MLP -> (l_b, tau) or fallback
 // ---------------------------------------------------------------------------
 
+constexpr float kRangePad = 0.1f;  // widening of the training range, as a fraction of its span
+
 __global__ void k_learned_apply(QState qs, int64_t nq, const float *__restrict__ feat,
                                 const float *__restrict__ norm, const uint16_t *__restrict__ pb,
                                 const int32_t *__restrict__ row_ptr,
@@ -365,11 +367,13 @@ __global__ void k_learned_apply(QState qs, int64_t nq, const float *__restrict__
         const float raw = feat[q * kF + f];
         x[f] = (raw - norm[f]) / norm[kF + f];
         // per-pair structural features (0..8) must lie in the range seen in
-        // training, widened by half its span; graph-level ones (lambda, eps,
-        // cost ratios) are left to the error head
+        // training, widened by a tenth of its span (the model extrapolates
+        // badly to hubs far beyond its training graphs; the greedy switch
+        // does better there); graph-level ones (lambda, eps, cost ratios) are
+        // left to the error head
         if (f <= 8) {
             const float lo = norm[2 * kF + f], hi = norm[3 * kF + f];
-            const float pad = 0.5f * (hi - lo);
+            const float pad = kRangePad * (hi - lo);
             if (raw < lo - pad || raw > hi + pad || fabsf(x[f]) > zmax) out_of_range = true;
         }
     }
