@@ -138,6 +138,8 @@ def training_graphs(scale=1.0):
         (lambda: I.chung_lu(300_000, 2.1, 12, 5005), q(3000), q(1000), q(750), (0.02, 0.05, 0.1), 4003),
         (lambda: I.rmat(17, 16, 0.57, 0.19, 0.19, 5006), q(2500), q(800), q(1000), (0.02, 0.05, 0.1),
          4004),
+        (lambda: I.rmat(19, 16, 0.57, 0.19, 0.19, 5007), q(1500), q(500), q(1000), (0.02, 0.05, 0.1),
+         4005),
     ]
 
 
