@@ -17,7 +17,7 @@ one by one:
     for walk steps, so they may go either way);
   * coverage (Definition 2.2): on 1,000 further pairs drawn without replacement,
     the fraction with |r' - r| > eps is consistent with the failure
-    probability delta = 0.01, judged by the Clopper-Pearson 95% interval.
+    probability delta = 0.01 by the Clopper-Pearson 95% interval.
 """
 
 import os
