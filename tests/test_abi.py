@@ -76,7 +76,8 @@ def test_graph_create_argument_errors():
 
 
 def test_generators_are_canonical_and_seeded():
-    for g in (I.erdos_renyi_path(500, 6, 1), I.chung_lu(2000, 2.1, 8, 2), I.rmat(10, 8, 0.57, 0.19, 0.19, 3)):
+    for g in (I.erdos_renyi_path(500, 6, 1), I.chung_lu(2000, 2.1, 8, 2), I.rmat(10, 8, 0.57, 0.19, 0.19, 3),
+              I.stochastic_block(3, 60, 0.4, 0.05, 4)):
         deg = g.degrees()
         assert deg.min() >= 1
         for v in range(0, g.n, max(1, g.n // 50)):
