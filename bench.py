@@ -68,10 +68,16 @@ def roofline_of(prof: dict, steps: int) -> tuple[dict, dict]:
     cands = [n for n in table if "achieved_GBs" in table[n]]
     dom = max(cands, key=lambda n: table[n]["ms_per_step"])
     ach = table[dom]["achieved_GBs"]
+    traffic = measured_traffic(dom)
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
             "alg_bytes_per_launch": table[dom]["alg_bytes_per_launch"],
             "avg_launch_us": round(table[dom]["avg_launch_us"], 3)}
+    if traffic:
+        # the rate of bytes actually moved (counters) over this run's launch time
+        moved = traffic / (table[dom]["avg_launch_us"] * 1e-6) / 1e9
+        roof["traffic_GBs"] = round(moved, 1)
+        roof["traffic_frac"] = round(moved / HBM_PEAK_GBS, 4)
     return roof, table
 
 

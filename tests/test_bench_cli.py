@@ -27,8 +27,9 @@ def _bench_module():
     return mod
 
 
-def test_roofline_takes_the_dominant_kernel_and_its_algorithmic_rate():
+def test_roofline_takes_the_dominant_kernel_and_its_algorithmic_rate(monkeypatch):
     b = _bench_module()
+    monkeypatch.setattr(b, "measured_traffic", lambda kernel: 2e9 if kernel == "walk" else None)
     prof = {
         "walk": {"launches": 20, "total_ms": 10.0, "alg_bytes": 4e9, "work_units": 1e8},
         "hop_light": {"launches": 2, "total_ms": 1.0, "alg_bytes": 1e9, "work_units": 0},
@@ -41,6 +42,9 @@ def test_roofline_takes_the_dominant_kernel_and_its_algorithmic_rate():
     assert roof["frac"] == round(roof["achieved"] / b.HBM_PEAK_GBS, 4)
     assert roof["alg_bytes_per_launch"] == 4e9 / 20
     assert roof["avg_launch_us"] == 500.0
+    assert roof["traffic"] == 2e9
+    assert roof["traffic_GBs"] == round(2e9 / 500e-6 / 1e9, 1)  # bytes moved per launch / launch time
+    assert roof["traffic_frac"] == round(roof["traffic_GBs"] / b.HBM_PEAK_GBS, 4)
     assert "unused" not in table and table["walk"]["launches_per_step"] == 10
     assert table["walk"]["units_per_launch"] == 1e8 / 20
 
