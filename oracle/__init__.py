@@ -30,6 +30,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "geer_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# The mutation tests point this at a copy of the checker built with a planted
+# mistake, to show that the pins catch it.
+_LIB_OVERRIDE = os.environ.get("GEER_ORACLE_LIB")
 _lib = None
 
 _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
@@ -60,9 +63,12 @@ def build(force: bool = True) -> str:
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
-            build(force=True)
-        L = ctypes.CDLL(_LIB_PATH)
+        if _LIB_OVERRIDE:
+            L = ctypes.CDLL(_LIB_OVERRIDE)
+        else:
+            if not os.path.exists(_LIB_PATH):
+                build(force=True)
+            L = ctypes.CDLL(_LIB_PATH)
         L.oracle_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
         L.oracle_smm_hop.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p]
         L.oracle_top2.argtypes = [ctypes.c_int64, _f64p, ctypes.POINTER(ctypes.c_double),

@@ -480,3 +480,169 @@ def test_geer_per_pair_tau_matches_uniform_tau():
         r2, st2 = oracle.geer(g.row_ptr, g.col_idx, s, t, 0.2, lam, tau=5, seed=2,
                               tau_per_pair=np.full(len(s), tau))
         assert np.array_equal(r1, r2) and np.array_equal(st1["batches_run"], st2["batches_run"])
+
+
+# ---------------------------------------------------------------------------
+# Two-sided pins: each of these fails when the checker's formula is off in
+# either direction (a length one too long, a bound too loose or too tight, a
+# stop one hop late), not only when it is unsafe.
+# ---------------------------------------------------------------------------
+
+def _tail(lam, l, ds, dt):
+    # the bound at the end of the proof of Theorem 3.1:
+    # |r - r_l| <= lam^(l+1) / (1 - lam) * (1/d(s) + 1/d(t))
+    return lam ** (l + 1) / (1.0 - lam) * (1.0 / ds + 1.0 / dt)
+
+
+def test_ell_is_smallest_length_meeting_the_tail_bound():
+    # Eq. (ell) solves the proof's tail bound for l: the returned l meets
+    # tail <= eps/2 and l - 1 does not (whenever l >= 1)
+    checked = 0
+    for ds in (1, 2, 3, 7, 50, 1000):
+        for dt in (1, 4, 13, 300):
+            for eps in (0.5, 0.2, 0.1, 0.05, 0.02, 0.01, 1e-3):
+                for lam in (0.1, 0.3, 0.5, 0.7, 0.866, 0.9, 0.97, 0.999):
+                    l = oracle.ell(ds, dt, eps, lam)
+                    assert l >= 0
+                    assert _tail(lam, l, ds, dt) <= eps / 2 * (1 + 1e-12)
+                    if l >= 1:
+                        prev = _tail(lam, l - 1, ds, dt)
+                        if abs(prev / (eps / 2) - 1.0) < 1e-9:
+                            continue  # exact tie: either length is a correct reading
+                        assert prev > eps / 2, (ds, dt, eps, lam, l)
+                        checked += 1
+    assert checked > 600
+
+
+def test_peng_ell_is_smallest_length_meeting_its_bound():
+    # Eq. (old-ell) is the same bound with 1/d(s) + 1/d(t) replaced by 2
+    checked = 0
+    for eps in (0.5, 0.2, 0.1, 0.05, 0.02, 0.01, 1e-3):
+        for lam in (0.1, 0.3, 0.5, 0.7, 0.866, 0.9, 0.97, 0.999):
+            l = oracle.ell_peng(eps, lam)
+            assert _tail(lam, l, 1, 1) <= eps / 2 * (1 + 1e-12)
+            if l >= 1:
+                assert _tail(lam, l - 1, 1, 1) > eps / 2
+                checked += 1
+    assert checked > 40
+
+
+def _two_paths():
+    # b - a - s - t - c - d  with s = 0, a = 1, b = 2, t = 3, c = 4, d = 5:
+    # a walk from s can alternate a, b, a, b, ... and one from t c, d, c, ...
+    return I.from_edges(6, np.array([[0, 1], [1, 2], [0, 3], [3, 4], [4, 5]]))
+
+
+@pytest.mark.parametrize("lf,half_psi", [(5, 3 * 0.6 + 2 * 0.25), (7, 4 * 0.6 + 3 * 0.25),
+                                         (6, 3 * 0.6 + 3 * 0.25)])
+def test_psi_is_attained_by_an_alternating_walk(lf, half_psi):
+    # Lemma 3.3's bound is tight: a walk that alternates between the largest
+    # and second-largest entries of x collects ceil(lf/2) max1 + floor(lf/2)
+    # max2.  Here x = 0.5 at a, 0.3 at b; y = 0.7 at c, 0.2 at d; d(s) = d(t)
+    # = 2, so psi/2 = ceil(lf/2) (0.25 + 0.35) + floor(lf/2) (0.15 + 0.1)
+    # (the expected values above, worked out by hand).  The largest sampled
+    # Z_k must equal psi/2: at odd lf this fixes which of max1 and max2 takes
+    # the ceiling, and equality fixes psi from above as well.
+    g = _two_paths()
+    deg = g.degrees()
+    x = np.zeros(6)
+    y = np.zeros(6)
+    x[1], x[2] = 0.5, 0.3
+    y[4], y[5] = 0.7, 0.2
+    m1s, m2s = oracle.top2(x)
+    m1t, m2t = oracle.top2(y)
+    psi = oracle.psi(lf, m1s, m2s, m1t, m2t, deg[0], deg[3])
+    assert psi == pytest.approx(2 * half_psi, rel=1e-14)
+    z = oracle.amc_samples(g.row_ptr, g.col_idx, 0, 3, x, y, lf, 2024, 0, 0, 20000)
+    assert np.all(np.abs(z) <= psi / 2 * (1 + 1e-14))
+    assert z.max() == pytest.approx(psi / 2, rel=1e-14)
+
+
+def test_bernstein_width_brackets_the_normal_quantile():
+    # Eq. (fx) at a large sample count: the range term vanishes and the width
+    # sqrt(2 var ln(3/delta) / n) must lie between the two-sided normal
+    # quantile z_{1-delta/2} sigma / sqrt(n) (the limit any valid bound must
+    # reach, central limit theorem) and 1.5 times it (sqrt(2 ln 300) / z_0.995
+    # = 1.31).  A two-point distribution {0, psi} with P(psi) = p has
+    # variance p (1 - p) psi^2.
+    from scipy.stats import norm
+
+    for delta in (0.01, 0.002):
+        for p in (0.5, 0.1, 0.01):
+            for psi in (1.0, 0.03):
+                n = 1e9
+                var = p * (1 - p) * psi ** 2
+                clt = norm.ppf(1 - delta / 2) * np.sqrt(var / n)
+                f = oracle.bernstein(n, var, psi, delta)
+                assert clt <= f <= 1.5 * clt, (delta, p, psi, f / clt)
+
+
+def test_bernstein_width_covers_the_mean_on_small_samples():
+    # Lemma 3.2 itself: |Z - E Z| < f(n, var_hat, psi, delta) on at least
+    # 1 - delta of repeated experiments, here with skewed two-point samples
+    # where the range term matters
+    rng = np.random.default_rng(8)
+    delta, reps = 0.05, 4000
+    for n, p in ((20, 0.05), (50, 0.2), (200, 0.5)):
+        zs = (rng.random((reps, n)) < p).astype(np.float64)
+        mean = zs.mean(axis=1)
+        var = np.maximum(0.0, (zs ** 2).mean(axis=1) - mean ** 2)
+        f = np.array([oracle.bernstein(n, v, 1.0, delta) for v in var])
+        assert np.mean(np.abs(mean - p) >= f) <= delta
+
+
+def test_greedy_switch_stops_at_the_first_hop_where_the_rule_holds():
+    # Eq. (smm-amc) is checked after every product (repeat-until): the greedy
+    # schedule must stop at the first hop l_b at which the support degree sum
+    # exceeds h(l - l_b), so the rule held at l_b (or l_b = l) and was false
+    # at every hop 1..l_b - 1.  Supports and psi are recomputed hop by hop
+    # from the checker's SMM vectors.
+    g = I.chung_lu(700, 2.1, 8, 61)
+    lam = oracle.lambda_dense(g.row_ptr, g.col_idx)
+    deg = g.degrees()
+    s, t = I.uniform_pairs(g.n, 120, 62)
+    tau, delta = 5, 0.01
+    deep = 0
+    for eps in (0.2, 0.02):
+        _, st = oracle.geer(g.row_ptr, g.col_idx, s, t, eps, lam, tau=tau, delta=delta, seed=3)
+        for j in range(len(s)):
+            l, lb = int(st["ell"][j]), int(st["ell_b"][j])
+            if l == 0:
+                assert lb == 0
+                continue
+            assert 1 <= lb <= l
+            for hop in range(1, lb + 1):
+                x, y, sx, sy, _ = oracle.smm_vectors(g.row_ptr, g.col_idx, s[j], t[j], hop)
+                supp = deg[sx].sum() + deg[sy].sum()
+                psi = oracle.psi(l - hop, *oracle.top2(x), *oracle.top2(y), deg[s[j]], deg[t[j]])
+                h = oracle.h_budget(oracle.eta_star(psi, eps, tau, delta), tau)
+                holds = supp > h
+                if hop < lb:
+                    assert not holds, (eps, j, hop, lb, supp, h)
+                elif lb < l:
+                    assert holds, (eps, j, hop, supp, h)
+            deep += lb >= 2
+    assert deep >= 20  # the one-hop-earlier check is exercised
+
+
+def test_mlp_reference_adam_steps_by_lr_with_bias_correction():
+    # Adam (Kingma & Ba, with bias correction): under a constant gradient the
+    # corrected moments are m_hat = g and v_hat = g^2 at every step, so each
+    # coordinate with a nonzero gradient moves by exactly lr (up to eps / |g|)
+    from oracle import mlp
+
+    rng = np.random.default_rng(4)
+    p = rng.normal(0, 1, mlp.P)
+    # gradients of either sign spanning five decades, all far above eps = 1e-8
+    g = rng.choice([-1.0, 1.0], mlp.P) * rng.uniform(1.0, 10.0, mlp.P) * 10.0 ** rng.integers(-3, 2, mlp.P)
+    g[::17] = 0.0
+    m = np.zeros(mlp.P)
+    v = np.zeros(mlp.P)
+    lr = 1e-3
+    for step in range(1, 6):
+        p2, m, v = mlp.adam_step(p, m, v, g, step, lr)
+        moved = p - p2
+        nz = g != 0
+        assert np.allclose(moved[nz], lr * np.sign(g[nz]), rtol=1e-4, atol=0)
+        assert np.all(moved[~nz] == 0)
+        p = p2
