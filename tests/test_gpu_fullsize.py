@@ -7,17 +7,18 @@ learned schedule and plain greedy schedule).  A sample of pairs is checked
 one by one:
 
   * |r' - r| <= eps against the exact resistance (Jacobi-PCG to 1e-10);
-  * each sampled answer equals the checker's FP64 GEER run with the same
-    per-pair schedule (l_b, tau) wherever the FP32 and FP64 runs take the
-    same walk-count decisions (relative 1e-5);
+  * every sampled pair is compared with the checker's FP64 GEER run (the
+    learned schedule's (l_b, tau) replayed): l exactly, r_b, psi and eta*
+    to FP32 precision, and any decision the two runs take differently is
+    shown to be an FP32 tie on the checker's side (tests/parity.py);
   * GPU lambda (Lanczos, widened by residuals) sits on or just above ARPACK's;
   * gain of the learned schedule: fewer SMM products than the greedy switch
     of the plain method and at least 1.2x its pairs/s (second, warm call of
     each, same pairs); walk steps are reported (the schedule trades products
     for walk steps, so they may go either way);
   * coverage (Definition 2.2): on 1,000 further pairs drawn without replacement,
-    the fraction with |r' - r| > eps is consistent with the failure
-    probability delta = 0.01 by the Clopper-Pearson 95% interval.
+    at most 10 (1%) have |r' - r| > eps, and the Clopper-Pearson 95%
+    interval of the failure rate is reported.
 """
 
 import os
@@ -27,6 +28,7 @@ import numpy as np
 import pytest
 
 import oracle
+import parity
 from paper_2312_06123_amd import inputs as I
 
 G = pytest.importorskip("paper_2312_06123_amd.geer")
@@ -83,12 +85,9 @@ def test_fullsize_learned_replay(bench_run):
     ro, sto = oracle.geer(g.row_ptr, g.col_idx, s[sample], t[sample], EPS, lam, seed=3002,
                           schedule="fixed", fixed_lb=st_l["ell_b"][sample], qid=sample,
                           tau_per_pair=st_l["tau"][sample])
-    assert np.array_equal(sto["ell"], st_l["ell"][sample])
     assert np.array_equal(sto["ell_b"], st_l["ell_b"][sample])
-    same = (sto["eta1"] == st_l["eta1"][sample]) & (sto["batches_run"] == st_l["batches_run"][sample])
-    assert same.mean() >= 0.9
-    got = r_l[sample][same]
-    assert np.all(np.abs(got - ro[same]) <= 1e-5 * np.maximum(1.0, np.abs(ro[same])))
+    parity.compare(g, s[sample], t[sample], EPS, lam, st_l[sample], sto, tau=None,
+                   tau_per_pair=st_l["tau"][sample], seed=3002, qid=sample, label="bench learned")
 
 
 @pytest.mark.gpu
@@ -96,12 +95,8 @@ def test_fullsize_plain_replay(bench_run):
     g, s, t, lam, r_l, st_l, r_p, st_p, sample = bench_run
     ro, sto = oracle.geer(g.row_ptr, g.col_idx, s[sample], t[sample], EPS, lam, seed=3002,
                           qid=sample)
-    assert np.array_equal(sto["ell"], st_p["ell"][sample])
-    same = ((sto["ell_b"] == st_p["ell_b"][sample]) & (sto["eta1"] == st_p["eta1"][sample]) &
-            (sto["batches_run"] == st_p["batches_run"][sample]))
-    assert same.mean() >= 0.9
-    got = r_p[sample][same]
-    assert np.all(np.abs(got - ro[same]) <= 1e-5 * np.maximum(1.0, np.abs(ro[same])))
+    parity.compare(g, s[sample], t[sample], EPS, lam, st_p[sample], sto, tau=5, seed=3002,
+                   qid=sample, label="bench plain")
 
 
 @pytest.mark.gpu
@@ -149,4 +144,6 @@ def test_fullsize_coverage(bench_run):
         lo, hi = clopper_pearson(fails, n_cov)
         print(f"coverage {name}: {n_cov - fails}/{n_cov} within eps; failure rate 95% CI "
               f"[{lo:.4f}, {hi:.4f}]; max |r' - r| = {np.abs(r[cov] - ex).max():.4f}", flush=True)
+        # Definition 2.2 with delta = 0.01: at least 99% of the pairs within eps
+        assert fails <= 10, (name, fails)
         assert lo <= DELTA
