@@ -27,6 +27,12 @@ sys.path.insert(0, ROOT)
 METRIC = ("query pairs/sec at ε=0.05 (batched+learned vs plain GEER, 1 GPU); "
           "SpMM HBM GB/s")
 HBM_PEAK_GBS = 8000.0
+# Useful bytes of one walk step: the row offsets of the current node (8 B),
+# the chosen column index (4 B) and the pair's two FP32 vector values at the
+# new node (8 B).  The kernel fetches a packed 8-byte record per step instead
+# of the first 12 bytes and reads no values for one-hop pairs; that smaller
+# figure is reported beside this one.
+WALK_STEP_BYTES = 20.0
 
 
 def log(msg: str) -> None:
@@ -50,8 +56,8 @@ def run_schedule(G, gg, ds, dt, de, dr, nq, steps, warmup, params_fn, torch):
     return {"value": nq / (ms / 1e3), "ms_per_step": ms, "profile": prof}
 
 
-def roofline_of(prof: dict, steps: int) -> tuple[dict, dict]:
-    """Roofline of the dominant kernel (largest total event time) and a per-kernel table."""
+def kernel_table(prof: dict, steps: int) -> dict:
+    """Per-kernel launches, event time and algorithmic bytes per step."""
     table = {}
     for name, r in prof.items():
         if r["launches"] == 0:
@@ -65,57 +71,115 @@ def roofline_of(prof: dict, steps: int) -> tuple[dict, dict]:
         if r["work_units"] > 0:
             entry["units_per_launch"] = r["work_units"] / r["launches"]
         table[name] = entry
+    return table
+
+
+def roofline_of(prof: dict, steps: int, workload: dict) -> tuple[dict, dict]:
+    """Roofline of the dominant kernel (largest total event time) and a per-kernel table.
+
+    The walk kernel's algorithmic bytes are WALK_STEP_BYTES per step; the
+    SpMM hops' are row offsets, column indices, the gathered rows once, the
+    written rows once and the inverse degrees (the library's byte count)."""
+    table = kernel_table(prof, steps)
     cands = [n for n in table if "achieved_GBs" in table[n]]
     dom = max(cands, key=lambda n: table[n]["ms_per_step"])
-    ach = table[dom]["achieved_GBs"]
-    traffic = measured_traffic(dom)
+    ent = table[dom]
+    if dom == "walk":
+        per_launch = WALK_STEP_BYTES * ent["units_per_launch"]
+    else:
+        per_launch = ent["alg_bytes_per_launch"]
+    ach = per_launch / (ent["avg_launch_us"] * 1e-6) / 1e9
+    traffic = measured_traffic(dom, workload)
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "alg_bytes_per_launch": table[dom]["alg_bytes_per_launch"],
-            "avg_launch_us": round(table[dom]["avg_launch_us"], 3)}
+            "alg_bytes_per_launch": per_launch,
+            "avg_launch_us": round(ent["avg_launch_us"], 3)}
+    if dom == "walk":
+        roof["bytes_per_step"] = WALK_STEP_BYTES
+        roof["steps_per_launch"] = ent["units_per_launch"]
+        roof["packed_record_model"] = {"alg_bytes_per_launch": ent["alg_bytes_per_launch"],
+                                       "achieved": round(ent["achieved_GBs"], 2),
+                                       "frac": round(ent["achieved_GBs"] / HBM_PEAK_GBS, 4)}
     if traffic:
-        # the rate of bytes actually moved (counters) over this run's launch time
-        moved = traffic / (table[dom]["avg_launch_us"] * 1e-6) / 1e9
+        # the rate of the bytes the counters saw leave the L2 (line fills from
+        # the Infinity Cache or HBM) over this run's launch time
+        moved = traffic / (ent["avg_launch_us"] * 1e-6) / 1e9
         roof["traffic_GBs"] = round(moved, 1)
         roof["traffic_frac"] = round(moved / HBM_PEAK_GBS, 4)
+        roof["traffic_note"] = "L2-to-fabric line traffic (FETCH_SIZE, WRITE_SIZE), not HBM alone"
     return roof, table
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch from the committed PMC record, or None if the
-    kernel's source changed since the counters were taken."""
+SOURCES_HASHED = ["paper_2312_06123_amd/csrc/amc.hip", "paper_2312_06123_amd/csrc/graph.hip",
+                  "paper_2312_06123_amd/csrc/query.hip", "paper_2312_06123_amd/csrc/smm.hip",
+                  "paper_2312_06123_amd/csrc/learned.hip"]
+
+
+def source_hashes() -> dict:
     import hashlib
 
+    out = {}
+    for rel in SOURCES_HASHED:
+        out[rel] = hashlib.sha256(open(os.path.join(ROOT, rel), "rb").read()).hexdigest()[:16]
+    return out
+
+
+def measured_traffic(kernel: str, workload: dict):
+    """Bytes per launch from the committed counter record, or None unless the
+    record was taken on this exact workload (graph, pairs, schedule, tile,
+    record width) with the current sources."""
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[kernel]
-        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
     except (OSError, KeyError, ValueError):
         return None
-    if hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_16"]:
+    if rec.get("workload") != workload or rec.get("sources") != source_hashes():
         return None
     return rec["traffic_bytes_per_launch"]
 
 
-def spmm_roofline(prof: dict) -> dict:
-    """Dense SpMM hop (light rows + heavy segments + heavy finish) against HBM peak."""
+def spmm_roofline(prof: dict, steps: int) -> dict:
+    """Dense SpMM hops (light rows + heavy segments + heavy finish) against HBM peak."""
     ks = [k for k in ("hop_light", "hop_segments", "hop_heavy_fin") if prof.get(k, {}).get("launches")]
     ms = sum(prof[k]["total_ms"] for k in ks)
     by = sum(prof[k]["alg_bytes"] for k in ks)
-    if ms <= 0:
+    units = sum(prof[k]["work_units"] for k in ks)
+    hops = prof.get("dense_hop", {}).get("launches", 0)
+    if ms <= 0 or not hops:
         return {"achieved": None}
     ach = by / (ms * 1e-3) / 1e9
+    nnz_cols = units / hops  # CSR entries x active columns per dense hop
     return {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "dense_hops": prof.get("dense_hop", {}).get("launches"),
-            "ms_total": round(ms, 3)}
+            "frac": round(ach / HBM_PEAK_GBS, 4), "dense_hops_per_step": hops / steps,
+            "ms_per_dense_hop": round(ms / hops, 4),
+            "alg_bytes_per_dense_hop": by / hops, "csr_entries_x_columns_per_hop": nnz_cols}
 
 
-def cpu_baseline(g, s, t, eps, lam, seed, budget_s):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    """Host threads this process may use: the CPUs it is allowed to run on,
+    capped by OMP_NUM_THREADS where the host sets a share for this GPU."""
+    n = len(os.sched_getaffinity(0))
+    share = os.environ.get("OMP_NUM_THREADS")
+    if share and share.isdigit() and int(share) > 0:
+        n = min(n, int(share))
+    return max(1, n)
+
+
+def _cpu_rate(g, s, t, eps, lam, seed, budget_s, threads, first=32):
     import numpy as np
 
     import oracle
 
-    threads = max(1, min(16, os.cpu_count() or 1))
-    done, elapsed, count = 0, 0.0, 32
+    done, elapsed, count = 0, 0.0, first
     while elapsed < budget_s and done < len(s):
         hi = min(len(s), done + count)
         t0 = time.perf_counter()
@@ -123,14 +187,85 @@ def cpu_baseline(g, s, t, eps, lam, seed, budget_s):
                     qid=np.arange(done, hi), threads=threads)
         dt_ = time.perf_counter() - t0
         elapsed += dt_
+        per_q = dt_ / max(1, hi - done)
         done = hi
-        per_q = dt_ / max(1, hi - (hi - count))
-        count = int(min(4096, max(32, (budget_s - elapsed) / max(per_q, 1e-6) / 2)))
-        log(f"cpu checker: {done} pairs in {elapsed:.1f} s")
+        count = int(min(4096, max(threads, (budget_s - elapsed) / max(per_q, 1e-6) / 2)))
+        log(f"cpu checker ({threads} threads): {done} pairs in {elapsed:.1f} s")
+    return done, elapsed
+
+
+def cpu_baseline(g, s, t, eps, lam, seed, budget_s):
+    """The checker's FP64 greedy GEER on the host: all allotted threads on the
+    first pairs of the workload, and one thread (the paper's protocol) on a
+    smaller sample."""
+    threads = host_threads()
+    done, elapsed = _cpu_rate(g, s, t, eps, lam, seed, budget_s, threads)
+    d1, e1 = _cpu_rate(g, s, t, eps, lam, seed, max(2.0, budget_s / 3), 1, first=4)
     return {"value": round(done / elapsed, 3), "unit": "query pairs/s", "cores": threads,
             "kind": "oracle",
             "sample": f"first {done} of the {len(s)} query pairs, FP64 GEER with the greedy "
-                      f"schedule, {threads} threads"}
+                      f"schedule, {threads} threads",
+            "cpu_model": cpu_model(), "host_cpus_visible": os.cpu_count(),
+            "single_thread": {"value": round(d1 / e1, 3), "unit": "query pairs/s",
+                              "sample": f"first {d1} query pairs, 1 thread"}}
+
+
+def held_out(G, I, torch, model_path, args):
+    """The learned checkpoint on a graph it was not trained or tuned on:
+    Chung-Lu n = 2,000,000 (the 1M configuration's parameters, seed 1004),
+    50,000 uniform pairs at eps = 0.05; learned schedule against plain GEER."""
+    import numpy as np
+
+    t0 = time.perf_counter()
+    g = I.chung_lu(2_000_000, 2.1, 20, 1004)
+    s, t = I.uniform_pairs(g.n, 50_000, 2004)
+    log(f"held-out graph n={g.n} nnz={g.nnz} ({time.perf_counter() - t0:.1f} s)")
+    gg = G.Graph(g.n, g.row_ptr32(), g.col_idx)
+    lam = G.geer_graph_compute_lambda(gg.handle, 400, 1e-8, 7)
+    ts, tt = I.uniform_pairs(g.n, 1024, 2104)
+    G.geer_autotune(gg.handle, ts, tt, args.eps)
+    model = G.Model(path=model_path)
+    ds = torch.from_numpy(s).cuda()
+    dt = torch.from_numpy(t).cuda()
+    de = torch.full((len(s),), args.eps, dtype=torch.float64, device="cuda")
+    dr = torch.zeros(len(s), dtype=torch.float64, device="cuda")
+    pl = lambda: G.geer_params_default(seed=3004, schedule=G.GEER_SCHEDULE_LEARNED,
+                                       model=model.handle.value)
+    pp = lambda: G.geer_params_default(seed=3004)
+    steps = 2
+    lr = run_schedule(G, gg, ds, dt, de, dr, len(s), steps, 1, pl, torch)
+    pr = run_schedule(G, gg, ds, dt, de, dr, len(s), steps, 1, pp, torch)
+    _, st_l = G.geer_query(gg.handle, s, t, args.eps, pl(), stats=True)
+    gg.close()
+    model.close()
+    log(f"held-out: learned {lr['value']:.0f} pairs/s, plain {pr['value']:.0f} pairs/s")
+    return {"workload": "chung-lu power-law n=2000000 gamma=2.1 mean degree 20, largest "
+                        "component (seed 1004, not a training graph); 50000 uniform pairs; eps=0.05",
+            "nodes": g.n, "csr_entries": g.nnz, "lambda": round(lam, 6), "steps": steps,
+            "learned_pairs_per_s": round(lr["value"], 2), "plain_pairs_per_s": round(pr["value"], 2),
+            "speedup_vs_plain": round(lr["value"] / pr["value"], 3),
+            "fallback_frac": round(float(st_l["fallback"].mean()), 4),
+            "mean_ell_b": round(float(st_l["ell_b"].mean()), 3)}
+
+
+def spmm_full_width(G, gg, s, t, eps, torch, steps=2):
+    """Dense SpMM hops at full batch width: the first 640 pairs with a fixed
+    SMM depth of 5, so hops 3-5 of every 64-pair batch run dense on all 128
+    columns (the SMM-only regime of the paper's comparison)."""
+    import numpy as np
+
+    nq = 640
+    ds = torch.from_numpy(np.ascontiguousarray(s[:nq])).cuda()
+    dt = torch.from_numpy(np.ascontiguousarray(t[:nq])).cuda()
+    de = torch.full((nq,), eps, dtype=torch.float64, device="cuda")
+    dr = torch.zeros(nq, dtype=torch.float64, device="cuda")
+    depth = np.full(nq, 5, dtype=np.int32)
+    pf = lambda: G.geer_params_default(seed=3002, schedule=G.GEER_SCHEDULE_FIXED,
+                                       fixed_ell_b=depth.ctypes.data)
+    run = run_schedule(G, gg, ds, dt, de, dr, nq, steps, 1, pf, torch)
+    out = spmm_roofline(run["profile"], steps)
+    out["workload"] = "first 640 pairs, fixed SMM depth 5 (hops 3-5 dense, 128 columns)"
+    return out
 
 
 def main() -> int:
@@ -149,13 +284,18 @@ def main() -> int:
                                                     "scheduler.geermlp"))
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (a cached entry launches no calibration work)")
-    ap.add_argument("--only", choices=["both", "learned", "plain"], default="both",
-                    help="time only one schedule (profiling runs)")
+    ap.add_argument("--only", choices=["both", "learned", "plain", "fixed"], default="both",
+                    help="time only one schedule (profiling runs); fixed: every pair at "
+                         "--fixed-depth")
     ap.add_argument("--pairs", choices=["uniform", "edge"], default="uniform",
                     help="query endpoints: uniform node pairs, or pairs that are edges (the "
                          "paper's second workload)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device copy of this many MiB (HBM counter calibration)")
+    ap.add_argument("--no-held-out", action="store_true",
+                    help="skip the learned-vs-plain run on the held-out 2M-node graph")
+    ap.add_argument("--fixed-depth", type=int, default=0,
+                    help="with --only fixed: the SMM depth of every pair")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the query set shards across GPUs with no "
@@ -210,7 +350,32 @@ def main() -> int:
                                      group_batches=args.group_batches,
                                      schedule=G.GEER_SCHEDULE_LEARNED, model=model.handle.value)
 
+    workload = {"graph": f"chung-lu n={args.nodes} seed=1002", "pairs": args.pairs,
+                "queries": len(s), "eps": args.eps, "col_tile": args.col_tile,
+                "group_batches": args.group_batches, "walk_record_bytes": 8}
+
+    def fixed_params():
+        depth = np.full(len(s), args.fixed_depth, dtype=np.int32)
+        fixed_params.keep = depth
+        return G.geer_params_default(seed=seed, col_tile=args.col_tile,
+                                     group_batches=args.group_batches,
+                                     schedule=G.GEER_SCHEDULE_FIXED, fixed_ell_b=depth.ctypes.data)
+
     plain = learned = None
+    if args.only == "fixed":
+        log(f"fixed SMM depth {args.fixed_depth}")
+        fixed = run_schedule(G, gg, ds, dt, de, dr, len(s), args.steps, args.warmup, fixed_params,
+                             torch)
+        log(f"fixed: {fixed['value']:.1f} pairs/s, {fixed['ms_per_step']:.1f} ms/step")
+        workload["schedule"] = f"fixed depth {args.fixed_depth}"
+        roof, table = roofline_of(fixed["profile"], args.steps, workload)
+        print(json.dumps({"metric": METRIC, "value": round(fixed["value"], 2),
+                          "unit": "query pairs/s", "only": "fixed", "steps": args.steps,
+                          "ms_per_step": round(fixed["ms_per_step"], 3), "roofline": roof,
+                          "spmm_roofline": spmm_roofline(fixed["profile"], args.steps),
+                          "kernels": table}), flush=True)
+        gg.close()
+        return 0
     if args.only in ("both", "plain"):
         log("plain GEER (greedy switch rule)")
         plain = run_schedule(G, gg, ds, dt, de, dr, len(s), args.steps, args.warmup, plain_params,
@@ -226,10 +391,12 @@ def main() -> int:
     if args.only != "both":
         # profiling run: one schedule, nothing else launched after the timed steps
         head = learned or plain
-        roof, table = roofline_of(head["profile"], args.steps)
+        workload["schedule"] = args.only
+        roof, table = roofline_of(head["profile"], args.steps, workload)
         print(json.dumps({"metric": METRIC, "value": round(head["value"], 2),
                           "unit": "query pairs/s", "only": args.only, "steps": args.steps,
                           "ms_per_step": round(head["ms_per_step"], 3), "roofline": roof,
+                          "spmm_roofline": spmm_roofline(head["profile"], args.steps),
                           "kernels": table}), flush=True)
         gg.close()
         return 0
@@ -237,7 +404,10 @@ def main() -> int:
     _, st_p = G.geer_query(gg.handle, s, t, args.eps, plain_params(), stats=True)
     head = learned
     head_name = "batched + learned schedule (greedy fallback)"
-    roof, table = roofline_of(head["profile"], args.steps)
+    workload["schedule"] = "learned"
+    roof, table = roofline_of(head["profile"], args.steps, workload)
+    log("dense SpMM at full batch width")
+    spmm_full = spmm_full_width(G, gg, s, t, args.eps, torch)
     out = {
         "metric": METRIC,
         "value": round(head["value"], 2),
@@ -270,15 +440,20 @@ def main() -> int:
                     "walk_steps": int((2 * st_l["walk_pairs"] * (st_l["ell"] - st_l["ell_b"])).sum()),
                     "max_abs_diff_vs_plain": round(float(np.max(np.abs(r_learned - r_plain))), 5)},
         "autotune": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in tune.items()},
-        "spmm_roofline": spmm_roofline(head["profile"]),
+        "spmm_roofline": dict(spmm_roofline(head["profile"], args.steps),
+                              workload="the dense hops of the learned schedule's steps"),
+        "spmm_roofline_full_width": spmm_full,
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                         for kk, vv in v.items()} for k, v in table.items()},
     }
+    out["finite_results"] = bool(np.all(np.isfinite(r_plain)) and np.all(np.isfinite(r_learned)))
+    gg.close()
+    if not args.no_held_out:
+        log("held-out graph: learned vs plain")
+        out["held_out"] = held_out(G, I, torch, args.model, args)
     if not args.no_cpu_baseline:
         log("CPU checker baseline")
         out["cpu_baseline"] = cpu_baseline(g, s, t, args.eps, lam, seed, args.cpu_seconds)
-    out["finite_results"] = bool(np.all(np.isfinite(r_plain)) and np.all(np.isfinite(r_learned)))
-    gg.close()
     print(json.dumps(out), flush=True)
     return 0
 
