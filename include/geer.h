@@ -257,7 +257,11 @@ geer_status geer_model_set_norm(geer_model *m, const float *mean, const float *s
                                 const float *lo, const float *hi);
 /* Cost ratios used as features: rho2 = cost of one unit of hop-2 push work,
  * rhod = cost of one dense hop of a 64-pair batch divided by 64, both in
- * units of geer_tuning.ns_per_walk_step (geer_autotune measures them). */
+ * units of geer_tuning.ns_per_walk_step (geer_autotune measures them).
+ * Stored rounded to the nearest power of sqrt(2), so timing noise of a few
+ * percent does not change the learned schedule or any answer: ratios within
+ * a factor 2^(1/8) of a grid point give bit-identical results.  Both must be
+ * positive and finite (else GEER_E_INVALID_ARG). */
 geer_status geer_graph_set_costs(geer_graph *g, double rho2, double rhod);
 /* Raw features of nq pairs: host float[nq * GEER_MLP_FEATURES]. */
 geer_status geer_features(geer_graph *g, int64_t nq, const int32_t *s, const int32_t *t,
@@ -290,7 +294,8 @@ typedef struct geer_tuning {
                                   as much */
     double ns_per_hop2_unit;   /* one unit of sparse hop-2 work (one CSR entry of one column) */
     double ns_per_dense_hop;   /* one dense hop of a 64-pair batch */
-    double rho2, rhod;         /* the cost ratios stored with geer_graph_set_costs */
+    double rho2, rhod;         /* the cost ratios as stored by geer_graph_set_costs
+                                  (rounded to a power of sqrt(2)) */
 } geer_tuning;
 
 /* Time the SpMM column tiles and measure the unit costs of the phases on a

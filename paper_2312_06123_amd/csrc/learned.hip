@@ -624,9 +624,15 @@ geer_status geer_model_set_norm(geer_model *m, const float *mean, const float *s
 geer_status geer_graph_set_costs(geer_graph *g, double rho2, double rhod)
 {
     if (!g) return fail(GEER_E_INVALID_ARG, "graph is NULL");
-    if (!(rho2 > 0.0) || !(rhod > 0.0)) return fail(GEER_E_INVALID_ARG, "cost ratios must be > 0");
-    g->rho2 = rho2;
-    g->rhod = rhod;
+    if (!(rho2 > 0.0) || !(rhod > 0.0) || std::isinf(rho2) || std::isinf(rhod))
+        return fail(GEER_E_INVALID_ARG, "cost ratios must be > 0 and finite");
+    // Timed ratios vary by a few percent from run to run; the stored values
+    // are rounded to the nearest power of 2^(1/2), so that the schedule (and
+    // every answer) stays the same unless a ratio moves across a grid
+    // boundary.  A ratio within 8% (2^(1/8)) of a grid point always maps to it.
+    auto snap = [](double r) { return std::exp2(0.5 * std::nearbyint(2.0 * std::log2(r))); };
+    g->rho2 = snap(rho2);
+    g->rhod = snap(rhod);
     return GEER_OK;
 }
 

@@ -195,17 +195,27 @@ __global__ __launch_bounds__(64) void k_hop1(QState qs, SlotArgs sa,
 // dense hop: gather over a range of CSR entries into per-lane accumulators
 // ----------------------------------------------------------------------------
 
+// A segment's sum has one fixed shape whatever the column tile: four
+// interleaved partial sums S_j over the entries i = j mod 4 (in increasing i),
+// combined as (S0 + S1) + (S2 + S3).  With NS = 64 / (KT/2) neighbour slots
+// per wavefront, slot `slot` takes the entries i = slot mod NS and keeps the
+// 4/NS partial sums S_slot, S_(slot+NS), ... in acc[].  The result of a
+// heavy row is therefore bit-identical for every column tile, so the tile
+// the autotuner picks from timings never changes an answer.
 template <class T, int KT>
 __device__ __forceinline__ void gather_range(const int32_t *__restrict__ col_idx,
                                              const T *__restrict__ in,
                                              const uint32_t *__restrict__ in_bits, int32_t b,
                                              int32_t e, int lane, int slot, int col, int bw,
-                                             typename Vec2<T>::type &acc, uint32_t &bacc)
+                                             typename Vec2<T>::type (&acc)[4 / (64 / (KT / 2))],
+                                             uint32_t &bacc)
 {
     using T2 = typename Vec2<T>::type;
     constexpr int LPR = KT / 2;
     constexpr int NS = 64 / LPR;
+    constexpr int A = 4 / NS;
     constexpr int U = 8;
+    static_assert(U % A == 0 && 64 % (U * NS) == 0, "entry classes must stay fixed per accumulator");
     // Every lane runs the same trip counts so that the index broadcasts
     // (cross-lane reads) always execute with the whole wavefront active.
     for (int32_t base = b; base < e; base += 64) {
@@ -236,27 +246,52 @@ __device__ __forceinline__ void gather_range(const int32_t *__restrict__ col_idx
                     x[i].y = T(0);
                 }
             }
+            // entry k0 + i*NS + slot lies in class (i*NS + slot) mod 4, i.e.
+            // partial sum i mod A of this slot
 #pragma unroll
             for (int i = 0; i < U; ++i) {
-                acc.x += x[i].x;
-                acc.y += x[i].y;
+                acc[i % A].x += x[i].x;
+                acc[i % A].y += x[i].y;
                 bacc |= w[i];
             }
         }
     }
 }
 
-// Reduce accumulators of the NS neighbour slots into slot 0.
+// Combine the partial sums of the NS neighbour slots into slot 0 as
+// (S0 + S1) + (S2 + S3).
 template <class T, int KT>
-__device__ __forceinline__ void reduce_slots(typename Vec2<T>::type &acc, uint32_t &bacc)
+__device__ __forceinline__ typename Vec2<T>::type
+reduce_slots(typename Vec2<T>::type (&acc)[4 / (64 / (KT / 2))], uint32_t &bacc)
 {
+    using T2 = typename Vec2<T>::type;
     constexpr int LPR = KT / 2;
+    constexpr int NS = 64 / LPR;
 #pragma unroll
-    for (int o = LPR; o < 64; o <<= 1) {
-        acc.x += __shfl_xor(acc.x, o);
-        acc.y += __shfl_xor(acc.y, o);
-        bacc |= __shfl_xor(bacc, o);
+    for (int o = LPR; o < 64; o <<= 1) bacc |= __shfl_xor(bacc, o);
+    T2 r;
+    if constexpr (NS == 4) {
+        // slot j holds S_j: (S0 + S1) at slot 0 and (S2 + S3) at slot 2, then both
+        T2 a = acc[0];
+        a.x += __shfl_xor(a.x, LPR);
+        a.y += __shfl_xor(a.y, LPR);
+        a.x += __shfl_xor(a.x, 2 * LPR);
+        a.y += __shfl_xor(a.y, 2 * LPR);
+        r = a;
+    } else if constexpr (NS == 2) {
+        // slot 0 holds S0, S2; slot 1 holds S1, S3
+        T2 p = acc[0], q = acc[1];
+        p.x += __shfl_xor(p.x, LPR);
+        p.y += __shfl_xor(p.y, LPR);
+        q.x += __shfl_xor(q.x, LPR);
+        q.y += __shfl_xor(q.y, LPR);
+        r.x = p.x + q.x;
+        r.y = p.y + q.y;
+    } else {
+        r.x = (acc[0].x + acc[1].x) + (acc[2].x + acc[3].x);
+        r.y = (acc[0].y + acc[1].y) + (acc[2].y + acc[3].y);
     }
+    return r;
 }
 
 // Write one finished row: values (active pairs only; a stopped pair's vectors
@@ -450,13 +485,13 @@ __global__ __launch_bounds__(256) void k_hop_segments(
     const int col = col0 + 2 * (lane % LPR);
     const int bw = col >> 5;
     for (int32_t sgi = blockIdx.x * 4 + wave; sgi < nseg; sgi += gridDim.x * 4) {
-        T2 acc;
-        acc.x = T(0);
-        acc.y = T(0);
+        T2 parts[4 / (64 / LPR)];
+#pragma unroll
+        for (int a = 0; a < 4 / (64 / LPR); ++a) parts[a].x = parts[a].y = T(0);
         uint32_t bacc = 0;
         gather_range<T, KT>(col_idx, in, in_bits, seg_b[sgi], seg_e[sgi], lane, slot, col, bw,
-                            acc, bacc);
-        reduce_slots<T, KT>(acc, bacc);
+                            parts, bacc);
+        const T2 acc = reduce_slots<T, KT>(parts, bacc);
         if (slot == 0) {
             *reinterpret_cast<T2 *>(segbuf + (size_t)sgi * kCols + col) = acc;
             if ((lane & 15) == 0) segbits[(size_t)sgi * kBitWords + bw] = bacc;

@@ -171,6 +171,8 @@ extern "C" geer_status geer_autotune(geer_graph *g, int64_t nq, const int32_t *s
     g->tuned_col_tile = tn.col_tile;
     for (int i = 0; i < 3; ++i) g->tile_ns[i] = tn_tile_ns[i];
     GEER_TRY(geer_graph_set_costs(g, tn.rho2, tn.rhod));
+    tn.rho2 = g->rho2;
+    tn.rhod = g->rhod;
     *out = tn;
     return GEER_OK;
 }

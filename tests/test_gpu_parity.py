@@ -73,6 +73,26 @@ def test_smm_vectors_match_checker(cl_graph, fp64, tile):
                 assert np.allclose(top2[j], m, rtol=tol, atol=0), (hops, j)
 
 
+@pytest.mark.parametrize("fp64", [False, True])
+def test_smm_tiles_bit_identical(cl_graph, fp64):
+    # The column tile (the autotuner picks it from timings) never changes a
+    # value: light rows sum their neighbours in CSR order and heavy-row
+    # segments in one fixed shape, whatever the tile.  Hubs above 256 entries
+    # take the segment path; the hub is a start node so its segments carry
+    # nonzero values from hop 2 on.
+    g, _ = cl_graph
+    s, t = I.uniform_pairs(g.n, 64, 17)
+    s[0] = 0
+    t[2] = 0
+    out = {}
+    with _graph(g) as gg:
+        for tile in (32, 64, 128):
+            out[tile] = G.geer_smm(gg.handle, s, t, 5, fp64=fp64, col_tile=tile)
+    for tile in (64, 128):
+        for a, b in zip(out[tile], out[32]):
+            assert np.array_equal(a, b), tile
+
+
 def test_smm_small_degree_graph_fp64_exact_structure(er_graph):
     g, _ = er_graph
     s, t = I.uniform_pairs(g.n, 64, 8)
