@@ -216,6 +216,36 @@ geer_status geer_amc(geer_graph *g, int32_t s, int32_t t, const double *x, const
                      double eps, int32_t lf, int32_t tau, double delta, uint64_t seed, uint32_t q,
                      uint32_t flags, double *rf_out, geer_query_stats *stats);
 
+/* ---- Allocation-free variant ------------------------------------------- */
+
+/* Bytes of the fixed device scratch array behind geer_amc_device_noalloc
+ * (one per device, held until the process ends). */
+#define GEER_AMC_SCRATCH_BYTES (16u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): geer_amc
+ * with device vectors and outputs, which calls no hipMalloc or hipFree and
+ * reserves nothing; its scratch (the pair's state, chunk prefix sums and
+ * per-chunk partial sums) lives in a static device array of
+ * GEER_AMC_SCRATCH_BYTES per device.
+ *   d_xy: device array of 2n values (float, or double with
+ *         GEER_FLAG_FP64_VECTORS), node-major: d_xy[2v] = x(v), d_xy[2v+1] = y(v);
+ *         finite and non-negative (else GEER_E_INVALID_ARG).
+ *   d_rf_out: device double[1] <- r_f.  d_stats: device geer_query_stats[1]
+ *         or NULL (ell fields -1).
+ *   stream: hipStream_t, or NULL for the library stream.  Returns when done.
+ * The results are bit-identical to geer_amc on the same values.  Limit: the
+ * largest AMC batch may need at most (GEER_AMC_SCRATCH_BYTES - 16384) / 16
+ * chunks of 32 walk pairs (about 3.4e7 walk pairs); a larger one returns
+ * GEER_E_OOM before any walk is run.  Every call on a device shares that
+ * device's array and overwrites what the last call left there: calls that
+ * overlap on one device (two host threads, two streams) race and must be
+ * serialised by the caller. */
+geer_status geer_amc_device_noalloc(geer_graph *g, int32_t s, int32_t t, const void *d_xy,
+                                    double eps, int32_t lf, int32_t tau, double delta,
+                                    uint64_t seed, uint32_t q, uint32_t flags, void *stream,
+                                    double *d_rf_out, geer_query_stats *d_stats);
+
 /* ---- Learned scheduler ------------------------------------------------- */
 
 /* A 3-layer MLP (GEER_MLP_FEATURES -> 64 -> 64 -> 3, ReLU) that predicts, per

@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgeer.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["graph.hip", "smm.hip", "amc.hip", "query.hip", "lanczos.hip", "learned.hip", "tune.hip"]
+SOURCES = ["graph.hip", "smm.hip", "amc.hip", "query.hip", "lanczos.hip", "learned.hip", "tune.hip",
+           "noalloc.hip"]
 
 HIP_FLAGS = [
     "-O3",

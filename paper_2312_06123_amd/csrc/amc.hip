@@ -171,7 +171,9 @@ __device__ __forceinline__ bool lds_row_contains(const int32_t *row, int32_t x)
 constexpr int kChunkOffLds = 2048;
 constexpr int kXcds = 8;  // accelerator complex dies of an MI355X
 
-template <class T, int RB>
+// VS: values per node in the vector buffer (kCols for batch slots, 2 for one
+// pair's caller vectors)
+template <class T, int RB, int VS>
 __global__ __launch_bounds__(256) void k_walk(QState qs, int64_t q0, int nq, int round,
                                               const int64_t *__restrict__ chunk_off,
                                               const int64_t *__restrict__ total_p,
@@ -262,7 +264,7 @@ __global__ __launch_bounds__(256) void k_walk(QState qs, int64_t q0, int nq, int
                     xv = lds_row_contains(s_rows[wv][0], u) ? inv : 0.0;
                     yv = lds_row_contains(s_rows[wv][1], u) ? inv : 0.0;
                 } else {
-                    T2 w = *reinterpret_cast<const T2 *>(pool + voff + (size_t)u * kCols);
+                    T2 w = *reinterpret_cast<const T2 *>(pool + voff + (size_t)u * VS);
                     xv = (double)w.x;
                     yv = (double)w.y;
                 }
@@ -331,16 +333,19 @@ __global__ __launch_bounds__(256) void k_amc_stop(QState qs, int64_t q0, int nq,
 }
 
 geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hipStream_t st,
-                      int walk_ilp)
+                      int walk_ilp, const AmcScratch *ext)
 {
     (void)walk_ilp;
     Workspace &ws = g->ws;
     if (grp.nq <= 0) return GEER_OK;
+    if (grp.vstride != kCols && grp.vstride != 2)
+        return fail(GEER_E_INVALID_ARG, "vector stride must be 128 or 2");
     const int nq = (int)grp.nq;
-    GEER_TRY(ws.chunk_off.reserve(((size_t)nq + 1) * sizeof(int64_t)));
-    int64_t *chunk_off = ws.chunk_off.as<int64_t>();
-    int64_t *d_total = ws.misc.as<int64_t>() + 8;
-    int64_t *d_bound = ws.misc.as<int64_t>() + 12;
+    if (!ext) GEER_TRY(ws.chunk_off.reserve(((size_t)nq + 1) * sizeof(int64_t)));
+    int64_t *chunk_off = ext ? ext->chunk_off : ws.chunk_off.as<int64_t>();
+    int64_t *misc = ext ? ext->misc : ws.misc.as<int64_t>();
+    int64_t *d_total = misc + 8;
+    int64_t *d_bound = misc + 12;
     // one host read per group: the chunk bound sizes the partials and the
     // grid, and the rounds then run without host synchronisation (rounds in
     // which no pair is left launch empty grids)
@@ -353,7 +358,14 @@ geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hip
     const int64_t bound = host[0];
     const int rounds = (int)std::min<int64_t>(host[2], c.tau);
     if (bound == 0 || rounds <= 0) return GEER_OK;
-    GEER_TRY(ws.zpart.reserve((size_t)bound * sizeof(double2)));
+    if (ext) {
+        if (bound > ext->zpart_cap)
+            return fail(GEER_E_OOM, "scratch cap exceeded: the AMC batches need " + std::to_string(bound) +
+                                        " chunk partials, the fixed scratch holds " +
+                                        std::to_string(ext->zpart_cap));
+    } else {
+        GEER_TRY(ws.zpart.reserve((size_t)bound * sizeof(double2)));
+    }
     // a CU holds 8 walk workgroups (32 VGPRs, 17 KB of LDS, 4 waves each);
     // the grid fills 7 of them, so the next group's SMM kernels, queued on the
     // other stream, always find room beside the walks
@@ -362,29 +374,35 @@ geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hip
     const uint32_t key0 = (uint32_t)c.seed, key1 = (uint32_t)(c.seed >> 32);
     const void *rec = g->d_walk_rec;
     const uint32_t sb = (uint32_t)g->rec_sb, sd = (uint32_t)g->rec_sd;
-    auto *zp = ws.zpart.as<double2>();
+    auto *zp = ext ? ext->zpart : ws.zpart.as<double2>();
     for (int round = 0; round < rounds; ++round) {
         // walk steps of the batch (all, and those reading SMM vectors) for the
         // profiler's byte count, else into scratch
         int counter = -1;
-        int64_t *d_steps = prof_counter(g, &counter);
-        if (!d_steps) d_steps = ws.misc.as<int64_t>() + 10;
+        int64_t *d_steps = ext ? nullptr : prof_counter(g, &counter);
+        if (!d_steps) d_steps = misc + 10;
         hipLaunchKernelGGL(k_amc_plan, dim3(1), dim3(1024), 0, st, c.qs, grp.q0, nq, round,
                            chunk_off, d_total, d_steps, g->d_row_ptr);
         GEER_HIP(hipGetLastError());
         for (int part = 0; part < kWalkParts; ++part) {
-            int tok = prof_begin(g, st);
-#define GEER_WALK_LAUNCH(T, RB)                                                                 \
-    hipLaunchKernelGGL((k_walk<T, RB>), dim3(blocks), dim3(256), 0, st, c.qs, grp.q0, nq, round, \
-                       chunk_off, d_total, g->d_row_ptr, g->d_col_idx, rec, sb, sd,             \
+            int tok = ext ? -1 : prof_begin(g, st);
+#define GEER_WALK_LAUNCH(T, RB, VS)                                                                 \
+    hipLaunchKernelGGL((k_walk<T, RB, VS>), dim3(blocks), dim3(256), 0, st, c.qs, grp.q0, nq, round, \
+                       chunk_off, d_total, g->d_row_ptr, g->d_col_idx, rec, sb, sd,                 \
                        (const T *)grp.pool, key0, key1, c.qid_offset, zp, part, kWalkParts)
-            if (grp.value_size == 4) {
-                if (g->walk_rec_bytes == 8) GEER_WALK_LAUNCH(float, 8);
-                else GEER_WALK_LAUNCH(float, 16);
+#define GEER_WALK_LAUNCH_T(T, VS)                       \
+    do {                                                \
+        if (g->walk_rec_bytes == 8) GEER_WALK_LAUNCH(T, 8, VS); \
+        else GEER_WALK_LAUNCH(T, 16, VS);               \
+    } while (0)
+            if (grp.vstride == kCols) {
+                if (grp.value_size == 4) GEER_WALK_LAUNCH_T(float, kCols);
+                else GEER_WALK_LAUNCH_T(double, kCols);
             } else {
-                if (g->walk_rec_bytes == 8) GEER_WALK_LAUNCH(double, 8);
-                else GEER_WALK_LAUNCH(double, 16);
+                if (grp.value_size == 4) GEER_WALK_LAUNCH_T(float, 2);
+                else GEER_WALK_LAUNCH_T(double, 2);
             }
+#undef GEER_WALK_LAUNCH_T
 #undef GEER_WALK_LAUNCH
             GEER_HIP(hipGetLastError());
             // per step: one walk record; steps of pairs whose vectors are
@@ -398,6 +416,51 @@ geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hip
                            round, chunk_off, zp, c.tau, c.delta);
         GEER_HIP(hipGetLastError());
     }
+    return GEER_OK;
+}
+
+// ----------------------------------------------------------------------------
+// one pair on caller vectors (Algorithm 1 as a phase of its own)
+// ----------------------------------------------------------------------------
+
+__global__ void k_amc_setup(QState qs, const int32_t *__restrict__ row_ptr, int32_t s, int32_t t,
+                            int32_t lf, double eps, int32_t tau, double delta, int64_t voff,
+                            const double *__restrict__ cs_m1, const double *__restrict__ cs_m2)
+{
+    const double ids = 1.0 / (row_ptr[s + 1] - row_ptr[s]);
+    const double idt = 1.0 / (row_ptr[t + 1] - row_ptr[t]);
+    qs.s[0] = s;
+    qs.t[0] = t;
+    qs.ord[0] = 0;
+    qs.eps[0] = eps;
+    qs.ell[0] = -1;
+    qs.lb[0] = -1;
+    qs.lf[0] = lf;
+    qs.vec_off[0] = voff;
+    qs.batches[0] = 0;
+    qs.walk_pairs[0] = 0;
+    qs.rb[0] = 0.0;
+    qs.rf[0] = 0.0;
+    qs.zsum[0] = qs.z2sum[0] = qs.var[0] = qs.f[0] = 0.0;
+    qs.supp_sum[0] = 0;
+    qs.fallback[0] = 0;
+    qs.tau_q[0] = tau;
+    double psi = lf > 0 ? psi_of(lf, cs_m1[0], cs_m2[0], cs_m1[1], cs_m2[1], ids, idt) : 0.0;
+    double es = lf > 0 ? eta_star_of(psi, eps, tau, delta) : 0.0;
+    qs.psi[0] = psi;
+    qs.eta_star[0] = es;
+    qs.eta1[0] = lf > 0 ? eta1_of(es, tau) : 0;
+    qs.active_amc[0] = qs.eta1[0] > 0 ? 1 : 0;
+    qs.stop[0] = qs.active_amc[0] ? GEER_STOP_CAP : GEER_STOP_NO_WALKS;
+}
+
+geer_status launch_amc_setup(const geer_graph *g, const QState &qs, int32_t s, int32_t t,
+                             int32_t lf, double eps, int32_t tau, double delta, int64_t voff,
+                             const double *cs_m1, const double *cs_m2, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_amc_setup, dim3(1), dim3(1), 0, st, qs, g->d_row_ptr, s, t, lf, eps, tau,
+                       delta, voff, cs_m1, cs_m2);
+    GEER_HIP(hipGetLastError());
     return GEER_OK;
 }
 

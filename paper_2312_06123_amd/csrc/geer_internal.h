@@ -42,6 +42,10 @@ constexpr int kBitWords = kCols / 32; // support bitmask words per node
 constexpr int kSegNnz = 256;          // rows longer than this are split into segments
 constexpr int kPairsPerChunk = 32;    // walk pairs per wavefront work item (64 lanes)
 constexpr int kLearnedTauMax = 8;     // largest AMC batch count the learned schedule picks
+// misc scratch layout (int64 words): [8] AMC chunk total of the current
+// round, [10, 12) walk steps of the round (when not profiled), [12, 15) AMC
+// chunk bound, overflow flag and largest batch count of the group
+constexpr int kMiscWords = 16;
 
 // ----------------------------------------------------------------------------
 // Device-resident growable buffer
@@ -385,18 +389,37 @@ geer_status launch_hop2_lds_group(geer_graph *g, const QueryCtx &c, const SlotAr
                                   int nslots, int value_size, hipStream_t st);
 // hop-2 partials -> column statistics for the pairs in each slot's hop-2 mask
 geer_status launch_colstat_group(geer_graph *g, const SlotArgs &sa, int nslots, hipStream_t st);
-geer_status launch_column_top2(geer_graph *g, const void *vec, int ncols, int value_size,
-                               hipStream_t st);
+// largest and second-largest entry of columns [0, ncols) of a node-major
+// vector buffer with `stride` values per node -> cs_m1[c], cs_m2[c]
+geer_status launch_column_top2(const geer_graph *g, const void *vec, int ncols, int stride,
+                               int value_size, double *cs_m1, double *cs_m2, hipStream_t st);
 
 struct AmcGroup {
     int64_t q0;      // first query of the group
     int64_t nq;      // queries in the group
     const void *pool;
     int value_size;
+    int vstride = kCols;  // values per node in the vector buffer (kCols, or 2 for one pair)
+};
+
+// AMC buffers supplied by the caller instead of the workspace (nothing is
+// reserved, no profiling): chunk_off[nq + 1], misc[kMiscWords], and room for
+// zpart_cap chunk partials; a group needing more chunks fails with GEER_E_OOM.
+struct AmcScratch {
+    int64_t *chunk_off;
+    int64_t *misc;
+    double2 *zpart;
+    int64_t zpart_cap;
 };
 
 geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hipStream_t st,
-                      int walk_ilp);
+                      int walk_ilp, const AmcScratch *ext = nullptr);
+// Algorithm 1 for the single query at slot 0 of qs with caller vectors at
+// element offset voff: sets s, t, ord, l_f and psi, eta*, eta_1 from the
+// top-2 entries in cs_m1[0..1], cs_m2[0..1] (Eq. Delta-st, Eq. etas-star)
+geer_status launch_amc_setup(const geer_graph *g, const QState &qs, int32_t s, int32_t t,
+                             int32_t lf, double eps, int32_t tau, double delta, int64_t voff,
+                             const double *cs_m1, const double *cs_m2, hipStream_t st);
 geer_status launch_finalize(geer_graph *g, const QueryCtx &c, double *d_r_out,
                             geer_query_stats *d_stats, hipStream_t st);
 geer_status launch_walk_traces(geer_graph *g, int32_t nw, const int32_t *start, const uint32_t *q,
@@ -417,6 +440,8 @@ geer_status launch_learned(geer_graph *g, const QueryCtx &c, const geer_model *m
                            int32_t tau_max, hipStream_t st);
 
 // Workspace helpers (query.hip)
+size_t qstate_bytes(int64_t cap);                      // bytes of the QState arrays for cap queries
+void qstate_carve(char *base, int64_t cap, QState *qs);  // lay them out at base
 geer_status ensure_qstate(geer_graph *g, int64_t nq, QState *qs);
 geer_status ensure_slots(geer_graph *g, int slots, int value_size);
 int grid_blocks_dense(const geer_graph *g);

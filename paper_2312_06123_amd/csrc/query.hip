@@ -8,20 +8,13 @@
 
 namespace geer {
 
-// misc scratch layout (int64 words): [8] AMC chunk total of the current
-// round, [10, 12) walk steps of the round (when not profiled), [12, 15) AMC
-// chunk bound, overflow flag and largest batch count of the group
-static constexpr int kMiscWords = 16;
-
-geer_status ensure_qstate(geer_graph *g, int64_t nq, QState *qs)
+size_t qstate_bytes(int64_t cap)
 {
-    Workspace &ws = g->ws;
-    const int64_t cap = std::max<int64_t>(nq, 1);
-    const size_t per = 14 * sizeof(int32_t) + 4 * sizeof(int64_t) + 10 * sizeof(double);
-    GEER_TRY(ws.qstate.reserve((size_t)cap * per + 64));
-    GEER_TRY(ws.misc.reserve((kMiscWords + 1024) * sizeof(int64_t)));
-    GEER_TRY(ws.colstat.reserve(kCols * (2 * sizeof(double) + sizeof(int64_t))));
-    char *p = ws.qstate.as<char>();
+    return (size_t)cap * (14 * sizeof(int32_t) + 14 * sizeof(int64_t)) + 64;
+}
+
+void qstate_carve(char *p, int64_t cap, QState *qs)
+{
     auto take = [&](auto *&dst, size_t elem) {
         dst = reinterpret_cast<std::remove_reference_t<decltype(dst)>>(p);
         p += (size_t)cap * elem;
@@ -55,6 +48,16 @@ geer_status ensure_qstate(geer_graph *g, int64_t nq, QState *qs)
     take(qs->tau_q, 4);
     take(qs->ord, 4);
     take(qs->h1w, 4);
+}
+
+geer_status ensure_qstate(geer_graph *g, int64_t nq, QState *qs)
+{
+    Workspace &ws = g->ws;
+    const int64_t cap = std::max<int64_t>(nq, 1);
+    GEER_TRY(ws.qstate.reserve(qstate_bytes(cap)));
+    GEER_TRY(ws.misc.reserve((kMiscWords + 1024) * sizeof(int64_t)));
+    GEER_TRY(ws.colstat.reserve(kCols * (2 * sizeof(double) + sizeof(int64_t))));
+    qstate_carve(ws.qstate.as<char>(), cap, qs);
     ws.nq_cap = cap;
     return GEER_OK;
 }
@@ -888,37 +891,6 @@ geer_status geer_walk_traces(geer_graph *g, int32_t nw, const int32_t *start, co
 
 }  // extern "C"
 
-namespace geer {
-
-__global__ void k_amc_setup(QState qs, const int32_t *__restrict__ row_ptr, int32_t lf,
-                            double eps, int32_t tau, double delta, int64_t voff,
-                            const double *__restrict__ cs_m1, const double *__restrict__ cs_m2)
-{
-    const double ids = 1.0 / (row_ptr[qs.s[0] + 1] - row_ptr[qs.s[0]]);
-    const double idt = 1.0 / (row_ptr[qs.t[0] + 1] - row_ptr[qs.t[0]]);
-    qs.eps[0] = eps;
-    qs.ell[0] = -1;
-    qs.lb[0] = -1;
-    qs.lf[0] = lf;
-    qs.vec_off[0] = voff;
-    qs.batches[0] = 0;
-    qs.walk_pairs[0] = 0;
-    qs.rb[0] = 0.0;
-    qs.rf[0] = 0.0;
-    qs.zsum[0] = qs.z2sum[0] = qs.var[0] = qs.f[0] = 0.0;
-    qs.supp_sum[0] = 0;
-    qs.fallback[0] = 0;
-    qs.tau_q[0] = tau;
-    double psi = lf > 0 ? psi_of(lf, cs_m1[0], cs_m2[0], cs_m1[1], cs_m2[1], ids, idt) : 0.0;
-    double es = lf > 0 ? eta_star_of(psi, eps, tau, delta) : 0.0;
-    qs.psi[0] = psi;
-    qs.eta_star[0] = es;
-    qs.eta1[0] = lf > 0 ? eta1_of(es, tau) : 0;
-    qs.active_amc[0] = qs.eta1[0] > 0 ? 1 : 0;
-    qs.stop[0] = qs.active_amc[0] ? GEER_STOP_CAP : GEER_STOP_NO_WALKS;
-}
-
-}  // namespace geer
 
 extern "C" geer_status geer_amc(geer_graph *g, int32_t s, int32_t t, const double *x,
                                 const double *y, double eps, int32_t lf, int32_t tau,
@@ -965,15 +937,10 @@ extern "C" geer_status geer_amc(geer_graph *g, int32_t s, int32_t t, const doubl
     GEER_HIP(hipMemcpy2D(sv.buf(0, 1), (size_t)kCols * vs, host.data(), (size_t)2 * vs, (size_t)2 * vs,
                          (size_t)n, hipMemcpyHostToDevice));
     c.stream = st;
-    const int32_t zero = 0;
-    GEER_HIP(hipMemcpyAsync(c.qs.s, &s, sizeof(int32_t), hipMemcpyHostToDevice, st));
-    GEER_HIP(hipMemcpyAsync(c.qs.t, &t, sizeof(int32_t), hipMemcpyHostToDevice, st));
-    GEER_HIP(hipMemcpyAsync(c.qs.ord, &zero, sizeof(int32_t), hipMemcpyHostToDevice, st));
-    GEER_TRY(launch_column_top2(g, sv.buf(0, 1), 2, vs, st));
     double *cs_m1 = g->ws.colstat.as<double>();
-    hipLaunchKernelGGL(k_amc_setup, dim3(1), dim3(1), 0, st, c.qs, g->d_row_ptr, lf, eps, tau, delta,
-                       sv.elem_off(0, 1), cs_m1, cs_m1 + kCols);
-    GEER_HIP(hipGetLastError());
+    GEER_TRY(launch_column_top2(g, sv.buf(0, 1), 2, kCols, vs, cs_m1, cs_m1 + kCols, st));
+    GEER_TRY(launch_amc_setup(g, c.qs, s, t, lf, eps, tau, delta, sv.elem_off(0, 1), cs_m1,
+                              cs_m1 + kCols, st));
     AmcGroup grp;
     grp.q0 = 0;
     grp.nq = 1;

@@ -950,12 +950,12 @@ geer_status launch_epilogue_group(geer_graph *g, const QueryCtx &c, const SlotAr
 
 template <class T>
 __global__ __launch_bounds__(256) void k_column_top2(const T *__restrict__ vec, int32_t n,
-                                                     double *__restrict__ cs_m1,
+                                                     int stride, double *__restrict__ cs_m1,
                                                      double *__restrict__ cs_m2)
 {
     const int c = blockIdx.x;
     T a1 = 0, a2 = 0;
-    for (int32_t v = threadIdx.x; v < n; v += blockDim.x) top2_push(a1, a2, vec[(size_t)v * kCols + c]);
+    for (int32_t v = threadIdx.x; v < n; v += blockDim.x) top2_push(a1, a2, vec[(size_t)v * stride + c]);
     __shared__ double s1[256], s2[256];
     s1[threadIdx.x] = (double)a1;
     s2[threadIdx.x] = (double)a2;
@@ -976,17 +976,15 @@ __global__ __launch_bounds__(256) void k_column_top2(const T *__restrict__ vec, 
     }
 }
 
-geer_status launch_column_top2(geer_graph *g, const void *vec, int ncols, int value_size,
-                               hipStream_t st)
+geer_status launch_column_top2(const geer_graph *g, const void *vec, int ncols, int stride,
+                               int value_size, double *cs_m1, double *cs_m2, hipStream_t st)
 {
-    double *cs_m1 = g->ws.colstat.as<double>();
-    double *cs_m2 = cs_m1 + kCols;
     if (value_size == 4)
         hipLaunchKernelGGL(k_column_top2<float>, dim3(ncols), dim3(256), 0, st,
-                           (const float *)vec, g->n, cs_m1, cs_m2);
+                           (const float *)vec, g->n, stride, cs_m1, cs_m2);
     else
         hipLaunchKernelGGL(k_column_top2<double>, dim3(ncols), dim3(256), 0, st,
-                           (const double *)vec, g->n, cs_m1, cs_m2);
+                           (const double *)vec, g->n, stride, cs_m1, cs_m2);
     GEER_HIP(hipGetLastError());
     return GEER_OK;
 }

@@ -50,6 +50,7 @@ EXPORTED = [
     "geer_model_get_params", "geer_model_set_params", "geer_model_set_norm",
     "geer_graph_set_costs", "geer_features", "geer_mlp_forward", "geer_mlp_grad",
     "geer_mlp_train", "geer_autotune", "geer_profile_enable", "geer_profile_read",
+    "geer_amc_device_noalloc",
 ]
 
 MLP_FEATURES = 13
@@ -127,6 +128,8 @@ _SIGNATURES = {
     "geer_smm": ([_vp, _i32, _vp, _vp, _i32, _u32, _i32, _vp, _vp, _vp, _vp], _i32),
     "geer_walk_traces": ([_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _u64, _vp], _i32),
     "geer_amc": ([_vp, _i32, _i32, _vp, _vp, _f64, _i32, _i32, _f64, _u64, _u32, _u32, _vp, _vp], _i32),
+    "geer_amc_device_noalloc": ([_vp, _i32, _i32, _vp, _f64, _i32, _i32, _f64, _u64, _u32, _u32, _vp,
+                                 _vp, _vp], _i32),
     "geer_last_error": ([], ctypes.c_char_p),
     "geer_version": ([], ctypes.c_char_p),
     "geer_model_create": ([_u64, ctypes.POINTER(_vp)], _i32),
@@ -320,6 +323,19 @@ def geer_amc(g, s: int, t: int, x, y, eps: float, lf: int, tau: int = 5, delta: 
                          float(delta), int(seed), int(q), GEER_FLAG_FP64_VECTORS if fp64 else 0,
                          ctypes.byref(rf), _ptr(st)))
     return rf.value, st[0]
+
+
+def geer_amc_device_noalloc(g, s: int, t: int, d_xy: int, eps: float, lf: int, d_rf: int,
+                            d_stats: int = 0, tau: int = 5, delta: float = 0.01, seed: int = 0,
+                            q: int = 0, fp64: bool = False, stream: int = 0) -> None:
+    """geer_amc on device memory with no allocation: d_xy (2n interleaved
+    values), d_rf (one double) and d_stats (one record, or 0) are device
+    addresses; stream is a hipStream_t handle or 0 for the library stream."""
+    _check(_lib.geer_amc_device_noalloc(g, int(s), int(t), ctypes.c_void_p(d_xy), float(eps), int(lf),
+                                        int(tau), float(delta), int(seed), int(q),
+                                        GEER_FLAG_FP64_VECTORS if fp64 else 0,
+                                        ctypes.c_void_p(stream or None), ctypes.c_void_p(d_rf),
+                                        ctypes.c_void_p(d_stats or None)))
 
 
 def geer_profile_enable(g, on: bool = True) -> None:
