@@ -388,6 +388,19 @@ def main() -> int:
                                learned_params, torch)
         r_learned = dr.cpu().numpy()
         log(f"learned: {learned['value']:.1f} pairs/s, {learned['ms_per_step']:.1f} ms/step")
+    if args.only == "both":
+        # the same calls with the known-depth groups captured in one hipGraph
+        # (the first call captures, the others replay it)
+        log("batched + learned schedule, captured launch graph")
+        graph_params = lambda: G.geer_params_default(
+            seed=seed, col_tile=args.col_tile, group_batches=args.group_batches,
+            schedule=G.GEER_SCHEDULE_LEARNED, model=model.handle.value,
+            flags=G.GEER_FLAG_GRAPH_LAUNCH)
+        learned_graph = run_schedule(G, gg, ds, dt, de, dr, len(s), args.steps, args.warmup,
+                                     graph_params, torch)
+        r_graph = dr.cpu().numpy()
+        log(f"learned, graph: {learned_graph['value']:.1f} pairs/s, "
+            f"{learned_graph['ms_per_step']:.1f} ms/step")
     if args.only != "both":
         # profiling run: one schedule, nothing else launched after the timed steps
         head = learned or plain
@@ -439,6 +452,13 @@ def main() -> int:
                     "tau_hist": np.bincount(st_l["tau"], minlength=9).tolist(),
                     "walk_steps": int((2 * st_l["walk_pairs"] * (st_l["ell"] - st_l["ell_b"])).sum()),
                     "max_abs_diff_vs_plain": round(float(np.max(np.abs(r_learned - r_plain))), 5)},
+        "learned_graph_launch": {
+            "value": round(learned_graph["value"], 2),
+            "ms_per_step": round(learned_graph["ms_per_step"], 3),
+            "graph_launches_per_step": learned_graph["profile"].get("graph", {}).get("launches", 0) / args.steps,
+            "graph_ms_per_step": round(learned_graph["profile"].get("graph", {}).get("total_ms", 0.0)
+                                       / args.steps, 3),
+            "bit_identical_to_direct": bool(np.array_equal(r_graph, r_learned))},
         "autotune": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in tune.items()},
         "spmm_roofline": dict(spmm_roofline(head["profile"], args.steps),
                               workload="the dense hops of the learned schedule's steps"),

@@ -72,8 +72,19 @@ enum {
 /* geer_params.flags */
 enum {
     GEER_FLAG_FP64_VECTORS = 1u << 0, /* keep SMM vectors in FP64 instead of FP32 */
-    GEER_FLAG_NO_GRAPH_CAPTURE = 1u << 1, /* accepted for compatibility: AMC rounds are always
-                                             launched directly on the stream */
+    GEER_FLAG_GRAPH_LAUNCH = 1u << 1, /* FIXED / LEARNED: after the depths are known (one
+                                         read of them), run the SMM and AMC launches of every
+                                         group of known depth as one captured hipGraph, and
+                                         replay that graph on a later call that derives the
+                                         same launches (same pairs, depths, batch counts and
+                                         buffers).  Results are bit-identical to the direct
+                                         launches.  Groups of the greedy switch (the GREEDY
+                                         schedule, LEARNED pairs that fall back) decide at
+                                         every hop from the vectors and are launched directly
+                                         after the graph.  The captured AMC rounds keep their
+                                         chunk partials in a reserved 256 MB buffer: a round
+                                         needing more (over 5.4e8 walk pairs in one group)
+                                         makes the call return GEER_E_OOM */
     GEER_FLAG_PENG_ELL = 1u << 2 /* l by Eq. (old-ell) (Peng et al.'s length, Section 3.1) for every
                                     pair instead of Eq. (ell): the paper's comparison variant */
 };

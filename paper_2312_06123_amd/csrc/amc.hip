@@ -33,23 +33,26 @@ __device__ __forceinline__ bool one_hop_from_graph(int32_t lb, int32_t ds, int32
 // plan: chunk prefix sums for batch `round` of the active queries of a group
 // ----------------------------------------------------------------------------
 
+// sticky (nullable): a fixed plan's overflow word; once set, no chunk is planned.
 __global__ __launch_bounds__(1024) void k_amc_plan(QState qs, int64_t q0, int nq, int round,
                                                    int64_t *__restrict__ chunk_off,
                                                    int64_t *__restrict__ total,
                                                    int64_t *__restrict__ steps,
-                                                   const int32_t *__restrict__ row_ptr)
+                                                   const int32_t *__restrict__ row_ptr,
+                                                   const int64_t *__restrict__ sticky)
 {
     __shared__ int64_t s_sum[1024];
     __shared__ unsigned long long s_steps, s_vsteps;
     if (threadIdx.x == 0) s_steps = s_vsteps = 0;
     __syncthreads();
+    const bool halt = sticky && *sticky != 0;
     const int tid = threadIdx.x;
     const int per = (nq + 1023) / 1024;
     const int a = min(nq, tid * per), b = min(nq, a + per);
     int64_t local = 0;
     for (int i = a; i < b; ++i) {
         int64_t q = qs.ord[q0 + i];
-        if (qs.active_amc[q]) {
+        if (!halt && qs.active_amc[q]) {
             int64_t eta = qs.eta1[q] << round;
             local += (eta + kPairsPerChunk - 1) / kPairsPerChunk;
             const unsigned long long st = (unsigned long long)(2 * eta * qs.lf[q]);
@@ -73,7 +76,7 @@ __global__ __launch_bounds__(1024) void k_amc_plan(QState qs, int64_t q0, int nq
     for (int i = a; i < b; ++i) {
         chunk_off[i] = run;
         int64_t q = qs.ord[q0 + i];
-        if (qs.active_amc[q]) {
+        if (!halt && qs.active_amc[q]) {
             int64_t eta = qs.eta1[q] << round;
             run += (eta + kPairsPerChunk - 1) / kPairsPerChunk;
         }
@@ -90,8 +93,11 @@ __global__ __launch_bounds__(1024) void k_amc_plan(QState qs, int64_t q0, int nq
 // batch is its last (eta_1 2^(tau_q - 1)), so the sum of those chunk counts
 // bounds every round's total.  out: [0] the bound, [1] overflow flag (a batch
 // of 2^32 walk pairs or more), [2] the largest per-pair batch count.
+// With a fixed plan, sticky (nullable) records a bound above cap (bit 0) or
+// a too large batch (bit 1) for the whole call.
 __global__ __launch_bounds__(1024) void k_amc_bound(QState qs, int64_t q0, int nq,
-                                                    int64_t *__restrict__ out)
+                                                    int64_t *__restrict__ out, int64_t cap,
+                                                    int64_t *__restrict__ sticky)
 {
     __shared__ unsigned long long s_chunks;
     __shared__ int s_over, s_tau;
@@ -125,6 +131,10 @@ __global__ __launch_bounds__(1024) void k_amc_bound(QState qs, int64_t q0, int n
         out[0] = (int64_t)s_chunks;
         out[1] = s_over;
         out[2] = s_tau;
+        if (sticky) {
+            if (s_over) *sticky |= 2;
+            else if ((int64_t)s_chunks > cap) *sticky |= 1;
+        }
     }
 }
 
@@ -346,29 +356,43 @@ geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hip
     int64_t *misc = ext ? ext->misc : ws.misc.as<int64_t>();
     int64_t *d_total = misc + 8;
     int64_t *d_bound = misc + 12;
-    // one host read per group: the chunk bound sizes the partials and the
-    // grid, and the rounds then run without host synchronisation (rounds in
-    // which no pair is left launch empty grids)
-    hipLaunchKernelGGL(k_amc_bound, dim3(1), dim3(1024), 0, st, c.qs, grp.q0, nq, d_bound);
+    // The chunk bound sizes the partials and the grid.  Normally it is read
+    // once per group and the rounds then run without host synchronisation
+    // (rounds in which no pair is left launch empty grids).  A fixed plan
+    // reads nothing: it runs its given rounds on a full grid over the
+    // reserved partials, and the bound kernel flags a group that would not fit.
+    hipLaunchKernelGGL(k_amc_bound, dim3(1), dim3(1024), 0, st, c.qs, grp.q0, nq, d_bound,
+                       grp.zpart_cap, grp.fixed_plan ? grp.sticky : nullptr);
     GEER_HIP(hipGetLastError());
-    int64_t host[3] = {0, 0, 0};
-    GEER_HIP(hipMemcpyAsync(host, d_bound, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    GEER_HIP(hipStreamSynchronize(st));
-    if (host[1] != 0) return fail(GEER_E_INVALID_ARG, "AMC batch exceeds 2^32 walk pairs for a query");
-    const int64_t bound = host[0];
-    const int rounds = (int)std::min<int64_t>(host[2], c.tau);
-    if (bound == 0 || rounds <= 0) return GEER_OK;
-    if (ext) {
-        if (bound > ext->zpart_cap)
-            return fail(GEER_E_OOM, "scratch cap exceeded: the AMC batches need " + std::to_string(bound) +
-                                        " chunk partials, the fixed scratch holds " +
-                                        std::to_string(ext->zpart_cap));
+    int64_t bound = 0;
+    int rounds = 0;
+    if (grp.fixed_plan) {
+        if (ext || !grp.sticky) return fail(GEER_E_INVALID_ARG, "fixed AMC plan needs the workspace partials");
+        bound = grp.zpart_cap;
+        rounds = std::min(grp.rounds, (int)c.tau);
+        if ((size_t)bound * sizeof(double2) > ws.zpart.bytes)
+            return fail(GEER_E_DEVICE, "fixed AMC plan: partials not reserved");
     } else {
-        GEER_TRY(ws.zpart.reserve((size_t)bound * sizeof(double2)));
+        int64_t host[3] = {0, 0, 0};
+        GEER_HIP(hipMemcpyAsync(host, d_bound, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        GEER_HIP(hipStreamSynchronize(st));
+        if (host[1] != 0) return fail(GEER_E_INVALID_ARG, "AMC batch exceeds 2^32 walk pairs for a query");
+        bound = host[0];
+        rounds = (int)std::min<int64_t>(host[2], c.tau);
+        if (ext) {
+            if (bound > ext->zpart_cap)
+                return fail(GEER_E_OOM, "scratch cap exceeded: the AMC batches need " + std::to_string(bound) +
+                                            " chunk partials, the fixed scratch holds " +
+                                            std::to_string(ext->zpart_cap));
+        } else if (bound > 0) {
+            GEER_TRY(ws.zpart.reserve((size_t)bound * sizeof(double2)));
+        }
     }
+    if (bound == 0 || rounds <= 0) return GEER_OK;
     // a CU holds 8 walk workgroups (32 VGPRs, 17 KB of LDS, 4 waves each);
     // the grid fills 7 of them, so the next group's SMM kernels, queued on the
-    // other stream, always find room beside the walks
+    // other stream, always find room beside the walks.  (Results do not depend
+    // on the grid: a chunk's partial is the same whichever wave walks it.)
     int blocks = (int)std::min<int64_t>((bound + 3) / 4, (int64_t)g->num_cus * kWalkBlocksPerCu);
     if (blocks >= kXcds) blocks -= blocks % kXcds;  // whole rounds over the XCDs
     const uint32_t key0 = (uint32_t)c.seed, key1 = (uint32_t)(c.seed >> 32);
@@ -382,7 +406,8 @@ geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hip
         int64_t *d_steps = ext ? nullptr : prof_counter(g, &counter);
         if (!d_steps) d_steps = misc + 10;
         hipLaunchKernelGGL(k_amc_plan, dim3(1), dim3(1024), 0, st, c.qs, grp.q0, nq, round,
-                           chunk_off, d_total, d_steps, g->d_row_ptr);
+                           chunk_off, d_total, d_steps, g->d_row_ptr,
+                           grp.fixed_plan ? grp.sticky : nullptr);
         GEER_HIP(hipGetLastError());
         for (int part = 0; part < kWalkParts; ++part) {
             int tok = ext ? -1 : prof_begin(g, st);

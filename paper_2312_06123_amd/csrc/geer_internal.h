@@ -46,14 +46,28 @@ constexpr int kLearnedTauMax = 8;     // largest AMC batch count the learned sch
 // round, [10, 12) walk steps of the round (when not profiled), [12, 15) AMC
 // chunk bound, overflow flag and largest batch count of the group
 constexpr int kMiscWords = 16;
+constexpr int kMiscSticky = 16;  // [16, 18): overflow word of a captured call (workspace misc only)
+// chunk partials reserved for a captured call's AMC rounds (2^24 x 16 B =
+// 256 MB: about 5.4e8 walk pairs in one round of one group)
+constexpr int64_t kFixedPlanChunks = int64_t(1) << 24;
 
 // ----------------------------------------------------------------------------
 // Device-resident growable buffer
 // ----------------------------------------------------------------------------
 
+// Set while a call's launch sequence is being captured into a hipGraph: a
+// buffer that would have to grow then fails instead of allocating (every
+// buffer the captured sequence uses is reserved before capture begins).
+extern thread_local bool t_capturing;
+
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
+    // a captured launch graph whose kernels may address this buffer: it is
+    // destroyed before the buffer is freed (memory freed while an executable
+    // graph that was launched more than once still refers to it was not
+    // returned to the device)
+    hipGraphExec_t *dependent = nullptr;
     geer_status reserve(size_t want);
     void release();
     template <class T> T *as() const { return static_cast<T *>(ptr); }
@@ -111,6 +125,7 @@ enum ProfKind {
     PK_HOP2_SPARSE,
     PK_HOP2_LDS,
     PK_DENSE_HOP,
+    PK_GRAPH,  // one launch of a captured call (all of its kernels)
     PK_COUNT
 };
 
@@ -188,6 +203,12 @@ struct geer_graph {
     int tuned_col_tile = 0;                // autotuner's SpMM column tile (0: not tuned)
     double tile_ns[3] = {0, 0, 0};         // measured time of one tile launch at 32/64/128 columns
     std::vector<int64_t> h_nbr_work;       // sum of neighbour degrees (= sparse hop-2 work)
+    // captured launch sequence of the last GEER_FLAG_GRAPH_LAUNCH call and
+    // everything its kernels' arguments were derived from (replayed when a
+    // later call derives the same)
+    hipGraphExec_t gexec = nullptr;
+    std::vector<unsigned char> gsig;
+    std::vector<char> gdirty;              // Workspace::a_dirty after the captured jobs
     geer::Workspace ws;
     geer::Profiler prof;
 };
@@ -374,6 +395,8 @@ enum { kHop1Stopped = 0, kHop1Continuing = 1, kHop1Clear = 2 };
 geer_status launch_hop1_select(geer_graph *g, const QueryCtx &c, const SlotArgs &sa, int slot0,
                                int nslots, int mode, hipStream_t st);
 geer_status launch_hop_dense(geer_graph *g, const HopArgs &a, int value_size, hipStream_t st);
+// reserve the buffers of a dense hop (partial statistics, heavy-row segments)
+geer_status reserve_dense(geer_graph *g, int value_size);
 // epilogue of hop `hop` (vectors in buffer `which`) for slots [0, nslots)
 geer_status launch_epilogue_group(geer_graph *g, const QueryCtx &c, const SlotArgs &sa,
                                   int nslots, int hop, int which, int value_size, hipStream_t st);
@@ -400,6 +423,14 @@ struct AmcGroup {
     const void *pool;
     int value_size;
     int vstride = kCols;  // values per node in the vector buffer (kCols, or 2 for one pair)
+    // fixed plan (no host read; capturable): run exactly `rounds` rounds on a
+    // full persistent grid with the chunk partials in the reserved zpart
+    // buffer of zpart_cap entries; a group needing more sets bit 0 of
+    // *sticky (a batch of 2^32 walk pairs or more: bit 1) and walks nothing
+    bool fixed_plan = false;
+    int rounds = 0;
+    int64_t zpart_cap = 0;
+    int64_t *sticky = nullptr;
 };
 
 // AMC buffers supplied by the caller instead of the workspace (nothing is
@@ -438,6 +469,9 @@ void prof_end_counted(geer_graph *g, int token, int kind, int counter, double pe
 
 geer_status launch_learned(geer_graph *g, const QueryCtx &c, const geer_model *m, float *d_feat,
                            int32_t tau_max, hipStream_t st);
+
+// every workspace buffer of a graph handle (graph.hip)
+std::vector<DevBuf *> workspace_bufs(geer_graph *g);
 
 // Workspace helpers (query.hip)
 size_t qstate_bytes(int64_t cap);                      // bytes of the QState arrays for cap queries

@@ -21,9 +21,19 @@ geer_status fail(geer_status st, const std::string &msg)
     return st;
 }
 
+thread_local bool t_capturing = false;
+
+std::vector<DevBuf *> workspace_bufs(geer_graph *g)
+{
+    Workspace &w = g->ws;
+    return {&w.pool, &w.bits,   &w.part, &w.segbuf, &w.colstat, &w.qstate, &w.chunk_off,
+            &w.zpart, &w.misc, &w.io,   &w.acc,    &w.meta,    &w.feat,   &w.hpart};
+}
+
 geer_status DevBuf::reserve(size_t want)
 {
     if (want <= bytes) return GEER_OK;
+    if (t_capturing) return fail(GEER_E_DEVICE, "buffer growth requested while capturing a launch graph");
     release();
     size_t cap = want + want / 8 + 256;
     hipError_t e = hipMalloc(&ptr, cap);
@@ -38,6 +48,10 @@ geer_status DevBuf::reserve(size_t want)
 
 void DevBuf::release()
 {
+    if (ptr && dependent && *dependent) {
+        (void)hipGraphExecDestroy(*dependent);
+        *dependent = nullptr;
+    }
     if (ptr) (void)hipFree(ptr);
     ptr = nullptr;
     bytes = 0;
@@ -409,6 +423,7 @@ geer_status geer_graph_create(int32_t n, const int32_t *row_ptr, const int32_t *
         return fail(GEER_E_DEVICE, "hipGetDeviceProperties failed");
     }
     g->num_cus = prop.multiProcessorCount;
+    for (DevBuf *b : workspace_bufs(g)) b->dependent = &g->gexec;
     if (hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) != hipSuccess) {
         delete g;
         return fail(GEER_E_DEVICE, "hipStreamCreate failed");
@@ -440,20 +455,18 @@ void geer_graph_destroy(geer_graph *g)
                     g->d_light_rows, g->d_heavy_rows, g->d_heavy_seg_start, g->d_seg_begin,
                     g->d_seg_end,    g->d_nbr_work,   g->d_min_nbr_deg,     g->d_walk_rec,
                     g->d_nbr_deg2};
+    if (g->stream2) (void)hipStreamSynchronize(g->stream2);
+    if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
+    g->gexec = nullptr;
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
-    DevBuf *bufs[] = {&g->ws.pool,    &g->ws.bits,   &g->ws.part,      &g->ws.segbuf,
-                      &g->ws.colstat, &g->ws.qstate, &g->ws.chunk_off, &g->ws.zpart,
-                      &g->ws.misc,    &g->ws.io,     &g->ws.acc,       &g->ws.meta,
-                      &g->ws.feat,    &g->ws.hpart};
-    for (DevBuf *b : bufs) b->release();
+    for (DevBuf *b : workspace_bufs(g)) b->release();
     for (ProfRec &r : g->prof.recs) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t e : g->prof.spare) (void)hipEventDestroy(e);
     if (g->prof.d_counters) (void)hipFree(g->prof.d_counters);
-    if (g->stream2) (void)hipStreamSynchronize(g->stream2);
     for (int i = 0; i < 2; ++i) {
         if (g->ev_smm[i]) (void)hipEventDestroy(g->ev_smm[i]);
         if (g->ev_clean[i]) (void)hipEventDestroy(g->ev_clean[i]);
@@ -484,7 +497,8 @@ geer_status geer_profile_read(geer_graph *g, geer_kernel_profile *out, int32_t c
     GEER_TRY(prof_flush(g));
     static const char *names[PK_COUNT] = {"hop_light", "hop_segments", "hop_heavy_fin", "hop1",
                                           "colstat", "epilogue", "walk", "amc_plan", "amc_stop",
-                                          "features", "mlp", "hop2_global", "hop2_lds", "dense_hop"};
+                                          "features", "mlp", "hop2_global", "hop2_lds", "dense_hop",
+                                          "graph"};
     int32_t k = 0;
     for (int i = 0; i < PK_COUNT && k < cap; ++i) {
         geer_kernel_profile &r = out[k++];

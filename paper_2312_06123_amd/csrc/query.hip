@@ -456,12 +456,28 @@ static geer_status check_params(const geer_params &p)
         return fail(GEER_E_INVALID_ARG, "col_tile must be 0, 32, 64 or 128");
     if (p.group_batches < 0) return fail(GEER_E_INVALID_ARG, "group_batches must be >= 0");
     if (p.walk_ilp != 0 && p.walk_ilp != 1) return fail(GEER_E_INVALID_ARG, "walk_ilp must be 0 or 1");
-    if (p.flags & ~(uint32_t)(GEER_FLAG_FP64_VECTORS | GEER_FLAG_NO_GRAPH_CAPTURE | GEER_FLAG_PENG_ELL))
+    if (p.flags & ~(uint32_t)(GEER_FLAG_FP64_VECTORS | GEER_FLAG_GRAPH_LAUNCH | GEER_FLAG_PENG_ELL))
         return fail(GEER_E_INVALID_ARG, "unknown flags");
     if (p.schedule == GEER_SCHEDULE_LEARNED && !p.model)
         return fail(GEER_E_MODEL, "LEARNED schedule needs a model");
     return GEER_OK;
 }
+
+// Everything a captured call's launches were derived from, as bytes: a later
+// call deriving the same bytes replays the captured graph.
+struct GraphSig {
+    std::vector<unsigned char> b;
+    template <class T> void add(const T &v)
+    {
+        const unsigned char *p = reinterpret_cast<const unsigned char *>(&v);
+        b.insert(b.end(), p, p + sizeof(T));
+    }
+    template <class T> void add_n(const T *v, size_t n)
+    {
+        const unsigned char *p = reinterpret_cast<const unsigned char *>(v);
+        b.insert(b.end(), p, p + n * sizeof(T));
+    }
+};
 
 // The whole query pipeline on device-resident inputs (already in qstate).
 // h_s / h_t: host copies of the pairs (used for planning only).
@@ -488,7 +504,10 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
     GEER_TRY(launch_init_queries(g, c, d_fixed, -1, c.stream));
     const bool learned = p.schedule == GEER_SCHEDULE_LEARNED;
     if (learned) c.tau = std::max(c.tau, kLearnedTauMax);
-    std::vector<int32_t> ord(c.nq), target(c.nq, 0);
+    // GEER_FLAG_GRAPH_LAUNCH: the groups with known depths run as one
+    // captured graph (a greedy schedule has none)
+    const bool graph_mode = (p.flags & GEER_FLAG_GRAPH_LAUNCH) && p.schedule != GEER_SCHEDULE_GREEDY;
+    std::vector<int32_t> ord(c.nq), target(c.nq, 0), taus(graph_mode ? c.nq : 0);
     for (int64_t i = 0; i < c.nq; ++i) ord[i] = (int32_t)i;
     int64_t n_static = 0;  // positions [0, n_static) run a static plan, the rest greedy
     if (p.schedule != GEER_SCHEDULE_GREEDY) {
@@ -500,6 +519,9 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
         // batches so that dense hops run on full batches, shallowest first
         // (the first group needs hop 1 only, so walks start at once)
         std::vector<int32_t> ellh(c.nq), act(c.nq), fb(c.nq);
+        if (graph_mode)
+            GEER_HIP(hipMemcpyAsync(taus.data(), c.qs.tau_q, c.nq * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                    c.stream));
         GEER_HIP(hipMemcpyAsync(target.data(), c.qs.lb_target, c.nq * sizeof(int32_t),
                                 hipMemcpyDeviceToHost, c.stream));
         GEER_HIP(hipMemcpyAsync(ellh.data(), c.qs.ell, c.nq * sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
@@ -548,9 +570,10 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
     };
     auto meta = [&](int set) { return SlotMeta{g->ws.meta.as<uint64_t>() + set * meta_words, G}; };
     std::vector<std::vector<BatchRec>> recs(sets, std::vector<BatchRec>(G));
+    // sB: the AMC stream (a second library stream when there are two slot
+    // sets); a captured range runs on sA alone (see below)
     hipStream_t sA = c.stream, sB = sets == 2 ? g->stream2 : c.stream;
     QueryCtx cB = c;
-    cB.stream = sB;
     // restore job i's slots to zero on sA once its walks (on sB) are done, so
     // that the cleanup runs beside the next job's walks instead of before them
     auto cleanup = [&](size_t i) -> geer_status {
@@ -560,8 +583,18 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
         if (sB != sA) GEER_HIP(hipStreamWaitEvent(sA, g->ev_clean[jb.set], 0));
         return cleanup_group(g, c, v, m, slot_args(g, v, m, jb.gp), (int)jb.gp.nbat, recs[jb.set]);
     };
+    // a fixed AMC plan (captured jobs): the reserved partials, the call's
+    // overflow word, and each group's rounds from its largest batch count
+    int64_t *sticky = g->ws.misc.as<int64_t>() + kMiscSticky;
+    int64_t zcap = 0;
+    auto group_rounds = [&](const Job &jb) {
+        int r = 1;
+        const int64_t pe = std::min<int64_t>(jb.gp.pend, jb.gp.p0 + jb.gp.nbat * B);
+        for (int64_t i = jb.gp.p0; i < pe; ++i) r = std::max(r, taus[ord[i]]);
+        return r;
+    };
     // AMC phase of job i on sB, after its SMM on sA
-    auto amc = [&](size_t i) -> geer_status {
+    auto amc = [&](size_t i, bool fixed) -> geer_status {
         const Job &jb = jobs[i];
         if (sB != sA) GEER_HIP(hipStreamWaitEvent(sB, g->ev_smm[jb.set], 0));
         AmcGroup grp;
@@ -569,26 +602,150 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
         grp.nq = std::min<int64_t>(jb.gp.pend, jb.gp.p0 + jb.gp.nbat * B) - grp.q0;
         grp.pool = view(jb.set).pool;
         grp.value_size = vs;
+        if (fixed) {
+            grp.fixed_plan = true;
+            grp.rounds = group_rounds(jb);
+            grp.zpart_cap = zcap;
+            grp.sticky = sticky;
+        }
+        cB.stream = sB;
         GEER_TRY(amc_phase(g, cB, grp, sB, p.walk_ilp));
         if (sB == sA) return cleanup(i);  // one stream: the next job may reuse the slots
         GEER_HIP(hipEventRecord(g->ev_clean[jb.set], sB));
         return GEER_OK;
     };
-    // the AMC phase of job i - 1 is queued (its chunk bound read first) before
-    // the SMM of job i, so both run at once on the two slot sets; job i - 2's
-    // cleanup (same slot set as job i, whose records it reads) comes first
-    for (size_t i = 0; i <= jobs.size(); ++i) {
-        if (i >= 1) GEER_TRY(amc(i - 1));
-        if (i == jobs.size()) break;
-        const Job &jb = jobs[i];
-        if (sets == 2 && i >= 2) GEER_TRY(cleanup(i - 2));
-        GEER_TRY(smm_group(g, c, view(jb.set), meta(jb.set), jb.gp, jb.is_static, target.data(), h_s,
-                           h_t, ord.data(), col_tile, max_hops, recs[jb.set]));
-        if (sets == 2) GEER_HIP(hipEventRecord(g->ev_smm[jb.set], sA));
+    // Jobs [j0, j1): the AMC phase of job i - 1 is queued (its chunk bound
+    // read first, unless the plan is fixed) before the SMM of job i, so both
+    // run at once on the two slot sets; job i - 2's cleanup (same slot set as
+    // job i, whose records it reads) comes first.  The last two cleanups
+    // also order sA after every walk on sB.
+    auto run_jobs = [&](size_t j0, size_t j1, bool fixed) -> geer_status {
+        for (size_t i = j0; i <= j1; ++i) {
+            if (i >= j0 + 1) GEER_TRY(amc(i - 1, fixed));
+            if (i == j1) break;
+            const Job &jb = jobs[i];
+            if (sB != sA && i >= j0 + 2) GEER_TRY(cleanup(i - 2));
+            GEER_TRY(smm_group(g, c, view(jb.set), meta(jb.set), jb.gp, jb.is_static, target.data(), h_s,
+                               h_t, ord.data(), col_tile, max_hops, recs[jb.set]));
+            if (sB != sA) GEER_HIP(hipEventRecord(g->ev_smm[jb.set], sA));
+        }
+        if (sB != sA)
+            for (size_t i = j1 >= j0 + 2 ? j1 - 2 : j0; i < j1; ++i) GEER_TRY(cleanup(i));
+        return GEER_OK;
+    };
+    size_t n_fixed = 0;  // jobs run by the captured graph
+    if (graph_mode)
+        while (n_fixed < jobs.size() && jobs[n_fixed].is_static) ++n_fixed;
+    if (n_fixed > 0) {
+        // reserve every buffer the captured jobs use, then capture them (or
+        // replay the graph of an earlier call that derived the same launches)
+        zcap = kFixedPlanChunks;
+        GEER_TRY(g->ws.zpart.reserve((size_t)zcap * sizeof(double2)));
+        GEER_TRY(g->ws.chunk_off.reserve(((size_t)G * B + 1) * sizeof(int64_t)));
+        GEER_TRY(reserve_dense(g, vs));
+        geer_status aerr = GEER_OK;
+        ensure_hop2_acc(g, G, sA, &aerr);
+        GEER_TRY(aerr);
+        GraphSig sig;
+        sig.add(c.nq);
+        sig.add(vs);
+        sig.add(B);
+        sig.add(G);
+        sig.add(sets);
+        sig.add(col_tile);
+        sig.add(n_static);
+        sig.add(n_fixed);
+        sig.add(zcap);
+        sig.add(c.tau);
+        sig.add(c.delta);
+        sig.add(c.seed);
+        sig.add(c.qid_offset);
+        sig.add(c.schedule);
+        sig.add(c.hop1_implicit);
+        sig.add(p.walk_ilp);
+        sig.add(sA);
+        sig.add(sB);
+        const Workspace &w = g->ws;
+        for (const DevBuf *b : {&w.pool, &w.bits, &w.part, &w.segbuf, &w.colstat, &w.hpart, &w.qstate,
+                                &w.chunk_off, &w.zpart, &w.misc, &w.acc, &w.meta})
+            sig.add(b->ptr);
+        sig.add(w.acc_slots);
+        sig.add(w.nq_cap);
+        sig.add_n(w.a_dirty.data(), w.a_dirty.size());
+        sig.add_n(g->tile_ns, 3);
+        for (int64_t i = 0; i < n_static; ++i) {
+            const int32_t q = ord[i];
+            sig.add(q);
+            sig.add(target[q]);
+            sig.add(taus[q]);
+            sig.add(h_s[q]);
+            sig.add(h_t[q]);
+        }
+        // the host-side state the captured jobs leave behind (slot records,
+        // dirty buffers) is what running them leaves: derive it by capturing
+        // again whenever the signature differs
+        const bool replay = g->gexec && sig.b == g->gsig;
+        std::vector<char> dirty_after;
+        if (replay) {
+            dirty_after = g->gdirty;
+        } else {
+            if (g->gexec) {
+                (void)hipGraphExecDestroy(g->gexec);
+                g->gexec = nullptr;
+                g->gsig.clear();
+            }
+            // The captured range runs on sA alone (SMM, AMC and cleanup of
+            // each group in turn): a graph with parallel branches, captured
+            // again after an earlier capture and later destroyed, at times
+            // kept the device memory its kernels addressed from being
+            // returned when freed (measured on MI355X, ROCm 7.2); linear
+            // graphs never did.
+            const hipStream_t sB_direct = sB;
+            sB = sA;
+            geer_status st = GEER_OK;
+            const hipError_t be = hipStreamBeginCapture(sA, hipStreamCaptureModeThreadLocal);
+            const bool prof_on = g->prof.on;
+            if (be == hipSuccess) {
+                g->prof.on = false;
+                t_capturing = true;
+                st = launch_zero(g, sticky, 2 * sizeof(int64_t), sA);
+                if (st == GEER_OK) st = run_jobs(0, n_fixed, true);
+                t_capturing = false;
+                g->prof.on = prof_on;
+            }
+            hipGraph_t graph = nullptr;
+            const hipError_t ce = be == hipSuccess ? hipStreamEndCapture(sA, &graph) : be;
+            sB = sB_direct;
+            if (st != GEER_OK || ce != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                (void)hipGetLastError();
+                return st != GEER_OK ? st : fail(GEER_E_DEVICE, std::string("hipStreamEndCapture: ") +
+                                                                      hipGetErrorString(ce));
+            }
+            const hipError_t ie = hipGraphInstantiate(&g->gexec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) {
+                g->gexec = nullptr;
+                return fail(GEER_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+            }
+            g->gsig = std::move(sig.b);
+            g->gdirty = w.a_dirty;
+        }
+        int tok = prof_begin(g, sA);
+        GEER_HIP(hipGraphLaunch(g->gexec, sA));
+        prof_end(g, tok, PK_GRAPH, 0.0, 1.0, sA);
+        if (replay) g->ws.a_dirty = dirty_after;
     }
-    // the last two jobs' cleanups also order sA after every walk on sB
-    if (sets == 2)
-        for (size_t i = jobs.size() >= 2 ? jobs.size() - 2 : 0; i < jobs.size(); ++i) GEER_TRY(cleanup(i));
+    GEER_TRY(run_jobs(n_fixed, jobs.size(), false));
+    if (n_fixed > 0) {
+        int64_t flag = 0;
+        GEER_HIP(hipMemcpyAsync(&flag, sticky, sizeof(flag), hipMemcpyDeviceToHost, sA));
+        GEER_HIP(hipStreamSynchronize(sA));
+        if (flag & 2) return fail(GEER_E_INVALID_ARG, "AMC batch exceeds 2^32 walk pairs for a query");
+        if (flag & 1)
+            return fail(GEER_E_OOM, "an AMC round of the captured plan needs more than " +
+                                        std::to_string(zcap) + " chunk partials");
+    }
     g->ws.in_use = false;
     return GEER_OK;
 }

@@ -685,15 +685,23 @@ static geer_status hop_dense_t(geer_graph *g, const HopArgs &a, hipStream_t st)
     return GEER_OK;
 }
 
+geer_status reserve_dense(geer_graph *g, int value_size)
+{
+    Workspace &ws = g->ws;
+    const size_t prows = (size_t)grid_blocks_dense(g) + heavy_fin_blocks(g);
+    GEER_TRY(ws.part.reserve(prows * kCols * (2 * sizeof(double) + sizeof(int64_t))));
+    GEER_TRY(ws.segbuf.reserve((size_t)std::max(g->n_seg, 1) *
+                               (kCols * (size_t)value_size + kBitWords * sizeof(uint32_t))));
+    return GEER_OK;
+}
+
 geer_status launch_hop_dense(geer_graph *g, const HopArgs &a, int value_size, hipStream_t st)
 {
     Workspace &ws = g->ws;
     const int nb = grid_blocks_dense(g);
     const int nf = heavy_fin_blocks(g);
     const size_t prows = (size_t)nb + nf;
-    GEER_TRY(ws.part.reserve(prows * kCols * (2 * sizeof(double) + sizeof(int64_t))));
-    GEER_TRY(ws.segbuf.reserve((size_t)std::max(g->n_seg, 1) *
-                               (kCols * (size_t)value_size + kBitWords * sizeof(uint32_t))));
+    GEER_TRY(reserve_dense(g, value_size));
     const int kt = a.col_tile;
     const int whole = prof_begin(g, st);
     for (int c0 = 0; c0 < kCols; c0 += kt) {
@@ -1323,7 +1331,7 @@ int ensure_hop2_acc(geer_graph *g, int want, hipStream_t st, geer_status *err)
 {
     Workspace &ws = g->ws;
     *err = GEER_OK;
-    if (ws.acc_slots >= want) return ws.acc_slots;
+    if (ws.acc_slots >= want || (t_capturing && ws.acc_slots > 0)) return ws.acc_slots;
     // one block of n x kCols 64-bit accumulators per slot, within a quarter
     // of the free device memory (at least one block)
     const size_t per = (size_t)g->n * kCols * sizeof(unsigned long long);

@@ -33,7 +33,7 @@ GEER_GRAPH_TRUSTED = 1
 GEER_GRAPH_WIDE_WALK_RECORDS = 2
 
 GEER_FLAG_FP64_VECTORS = 1
-GEER_FLAG_NO_GRAPH_CAPTURE = 2
+GEER_FLAG_GRAPH_LAUNCH = 2
 GEER_FLAG_PENG_ELL = 4
 
 GEER_STOP_SAME_NODE = 0
