@@ -67,6 +67,7 @@ def kernel_table(prof: dict, steps: int) -> dict:
                  "avg_launch_us": 1e3 * r["total_ms"] / r["launches"]}
         if r["alg_bytes"] > 0 and r["total_ms"] > 0:
             entry["achieved_GBs"] = r["alg_bytes"] / (r["total_ms"] * 1e-3) / 1e9
+            entry["frac"] = entry["achieved_GBs"] / HBM_PEAK_GBS
             entry["alg_bytes_per_launch"] = r["alg_bytes"] / r["launches"]
         if r["work_units"] > 0:
             entry["units_per_launch"] = r["work_units"] / r["launches"]

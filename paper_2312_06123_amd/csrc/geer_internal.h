@@ -312,6 +312,7 @@ __host__ __device__ inline double bernstein_of(double nz, double var, double psi
 constexpr int32_t kMemberRowMax = 256;
 
 constexpr int kPushSplit = 8;       // blocks per column of the global sparse hop 2
+constexpr double kHop2UnitBytes = 12.0;  // profiler: 4-byte index + 8-byte accumulator per pushed entry
 constexpr int kHashLoadMax = 9830;  // columns with more hop-2 work use the global path
 
 // Where the batches of a group live.  Batch k of the group holds the pairs at
@@ -460,7 +461,8 @@ geer_status launch_walk_traces(geer_graph *g, int32_t nw, const int32_t *start, 
 // Profiling helpers (graph.hip): bracket a launch with events when enabled.
 int prof_begin(geer_graph *g, hipStream_t st);
 void prof_end(geer_graph *g, int token, int kind, double bytes, double units, hipStream_t st);
-void prof_add_units(geer_graph *g, int kind, double units);
+// host-known work of a launch (and its algorithmic bytes) booked on a kind
+void prof_add_units(geer_graph *g, int kind, double units, double bytes = 0.0);
 // A device slot of two int64 counters for a counted record, or nullptr when
 // profiling is off (kernels then write their counts to scratch).
 int64_t *prof_counter(geer_graph *g, int *index);

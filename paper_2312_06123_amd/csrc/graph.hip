@@ -93,9 +93,12 @@ void prof_end(geer_graph *g, int token, int kind, double bytes, double units, hi
     (void)hipEventRecord(r.b, st);
 }
 
-void prof_add_units(geer_graph *g, int kind, double units)
+void prof_add_units(geer_graph *g, int kind, double units, double bytes)
 {
-    if (g->prof.on) g->prof.units[kind] += units;
+    if (g->prof.on) {
+        g->prof.units[kind] += units;
+        g->prof.bytes[kind] += bytes;
+    }
 }
 
 static geer_status prof_flush(geer_graph *g)

@@ -238,7 +238,7 @@ static geer_status run_level(geer_graph *g, const QueryCtx &c, const SlotView &s
         for (int k = 0; k < nbat; ++k) {
             if (!hm[k]) continue;
             uint64_t m_lds[2] = {0, 0}, m_glob[2] = {0, 0};
-            double work = 0.0;
+            double work = 0.0, work_lds = 0.0;
             const int64_t q0 = slot_q0(sa, k);
             for (int j = 0; j < slot_nb(sa, k); ++j) {
                 if (!((hm[k] >> j) & 1ull)) continue;
@@ -247,8 +247,12 @@ static geer_status run_level(geer_graph *g, const QueryCtx &c, const SlotView &s
                     const int c2 = 2 * j + side;
                     const int64_t wk = g->h_nbr_work[side ? h_t[q] : h_s[q]];
                     work += (double)wk;
-                    if (wk <= kHashLoadMax) m_lds[c2 >> 6] |= 1ull << (c2 & 63);
-                    else m_glob[c2 >> 6] |= 1ull << (c2 & 63);
+                    if (wk <= kHashLoadMax) {
+                        m_lds[c2 >> 6] |= 1ull << (c2 & 63);
+                        work_lds += (double)wk;
+                    } else {
+                        m_glob[c2 >> 6] |= 1ull << (c2 & 63);
+                    }
                 }
             }
             if (work > 2.0 * (double)g->nnz) continue;
@@ -262,7 +266,10 @@ static geer_status run_level(geer_graph *g, const QueryCtx &c, const SlotView &s
             pw[1] = m_lds[1];
             pw[2] = m_glob[0];
             pw[3] = m_glob[1];
-            prof_add_units(g, PK_HOP2_LDS, work);
+            // algorithmic bytes of the push: per unit (one CSR entry of a
+            // neighbour's row) its 4-byte index and an 8-byte accumulator update
+            prof_add_units(g, PK_HOP2_LDS, work_lds, kHop2UnitBytes * work_lds);
+            prof_add_units(g, PK_HOP2_SPARSE, work - work_lds, kHop2UnitBytes * (work - work_lds));
         }
         if (any) {
             for (int k = 0; k < nbat; ++k)

@@ -755,66 +755,71 @@ geer_status launch_hop1_group(geer_graph *g, const QueryCtx &c, const SlotArgs &
     return GEER_OK;
 }
 
-// Selective hop-1 scatter (modes in geer_internal.h): one block per slot.
-// Each thread tests one pair; the pairs to write (or clear) are listed in LDS
-// and each wavefront then takes whole pairs (both columns, then the pair's
-// flag), so a flag is never read and reset by different wavefronts.
+// Clear a profiler counter pair (device counts are added to it).
+__global__ void k_zero_counter(int64_t *c)
+{
+    if (threadIdx.x < 2) c[threadIdx.x] = 0;
+}
+
+// Selective hop-1 scatter (modes in geer_internal.h).  Block (k, y) holds
+// four wavefronts; wavefront w takes pair j = y + 16 w of slot k: it decides
+// whether the pair's columns are written (or cleared), scatters both rows
+// and sets the pair's flag, so a flag is never read and reset by different
+// wavefronts.  Every pair of every slot has a wavefront of its own, and a
+// group's hub rows are scattered side by side.  entries (nullable, for the
+// profiler): CSR entries scattered, summed over the launch.
+constexpr int kHop1Split = kMaxPairs / 4;
+
 template <class T>
 __global__ __launch_bounds__(256) void k_hop1_select(QState qs, SlotArgs sa, int slot0, int mode,
                                                      const int32_t *__restrict__ row_ptr,
                                                      const int32_t *__restrict__ col_idx,
-                                                     const T *__restrict__ inv_deg)
+                                                     const T *__restrict__ inv_deg,
+                                                     unsigned long long *__restrict__ entries)
 {
-    __shared__ int32_t s_list[kMaxPairs];
-    __shared__ int32_t s_cnt;
     const int k = slot0 + (int)blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nb = slot_nb(sa, k);
-    if (threadIdx.x == 0) s_cnt = 0;
-    __syncthreads();
-    if ((int)threadIdx.x < nb) {
-        const int j = threadIdx.x;
-        const int64_t q = qs.ord[slot_q0(sa, k) + j];
-        bool need;
-        if (mode == kHop1Clear) {
-            need = qs.h1w[q] != 0;
-        } else if (qs.h1w[q] || qs.lb[q] != 1) {
-            need = false;
-        } else if (mode == kHop1Stopped) {
-            // the walk kernel evaluates the vector from LDS rows when both rows fit
-            const int32_t s = qs.s[q], t = qs.t[q];
-            const int32_t ds = row_ptr[s + 1] - row_ptr[s], dt = row_ptr[t + 1] - row_ptr[t];
-            need = !qs.active_smm[q] && (ds > kMemberRowMax || dt > kMemberRowMax);
-        } else {
-            need = qs.active_smm[q] != 0;
-        }
-        if (need) s_list[atomicAdd(&s_cnt, 1)] = j;
+    const int j = (int)blockIdx.y + kHop1Split * wave;
+    if (j >= slot_nb(sa, k)) return;
+    const int64_t q = qs.ord[slot_q0(sa, k) + j];
+    const int32_t s = qs.s[q], t = qs.t[q];
+    bool need;
+    if (mode == kHop1Clear) {
+        need = qs.h1w[q] != 0;
+    } else if (qs.h1w[q] || qs.lb[q] != 1) {
+        need = false;
+    } else if (mode == kHop1Stopped) {
+        // the walk kernel evaluates the vector from LDS rows when both rows fit
+        const int32_t ds = row_ptr[s + 1] - row_ptr[s], dt = row_ptr[t + 1] - row_ptr[t];
+        need = !qs.active_smm[q] && (ds > kMemberRowMax || dt > kMemberRowMax);
+    } else {
+        need = qs.active_smm[q] != 0;
     }
-    __syncthreads();
-    const int cnt = s_cnt;
+    if (!need) return;
     T *h1 = slot_buf<T>(sa, k, 0);
     uint32_t *h1_bits = slot_bits(sa, k, 0);
-    for (int i = wave; i < cnt; i += 4) {
-        const int j = s_list[i];
-        const int64_t q = qs.ord[slot_q0(sa, k) + j];
-        const int32_t s = qs.s[q], t = qs.t[q];
-        for (int side = 0; side < 2; ++side) {
-            const int c = 2 * j + side;
-            const int32_t u = side ? t : s;
-            const uint32_t bit = 1u << (c & 31);
-            for (int32_t e = row_ptr[u] + lane; e < row_ptr[u + 1]; e += 64) {
-                const int32_t v = col_idx[e];
-                uint32_t *bw = h1_bits + (size_t)v * kBitWords + (c >> 5);
-                if (mode == kHop1Clear) {
-                    h1[(size_t)v * kCols + c] = T(0);
-                    atomicAnd(bw, ~bit);
-                } else {
-                    h1[(size_t)v * kCols + c] = inv_deg[v];
-                    atomicOr(bw, bit);
-                }
+    int64_t cnt = 0;
+    for (int side = 0; side < 2; ++side) {
+        const int c = 2 * j + side;
+        const int32_t u = side ? t : s;
+        const uint32_t bit = 1u << (c & 31);
+        const int32_t b = row_ptr[u], e1 = row_ptr[u + 1];
+        cnt += e1 - b;
+        for (int32_t e = b + lane; e < e1; e += 64) {
+            const int32_t v = col_idx[e];
+            uint32_t *bw = h1_bits + (size_t)v * kBitWords + (c >> 5);
+            if (mode == kHop1Clear) {
+                h1[(size_t)v * kCols + c] = T(0);
+                atomicAnd(bw, ~bit);
+            } else {
+                h1[(size_t)v * kCols + c] = inv_deg[v];
+                atomicOr(bw, bit);
             }
         }
-        if (lane == 0) qs.h1w[q] = mode == kHop1Clear ? 0 : 1;
+    }
+    if (lane == 0) {
+        qs.h1w[q] = mode == kHop1Clear ? 0 : 1;
+        if (entries) atomicAdd(entries, (unsigned long long)cnt);
     }
 }
 
@@ -822,14 +827,21 @@ geer_status launch_hop1_select(geer_graph *g, const QueryCtx &c, const SlotArgs 
                                int nslots, int mode, hipStream_t st)
 {
     if (nslots <= 0) return GEER_OK;
+    // profiled: CSR entries scattered, each a 4-byte index read, a value
+    // written and a 4-byte support word updated
+    int counter = -1;
+    int64_t *d_cnt = prof_counter(g, &counter);
     int tok = prof_begin(g, st);
+    unsigned long long *ent = reinterpret_cast<unsigned long long *>(d_cnt);
+    if (d_cnt) hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, st, d_cnt);
+    const dim3 grid(nslots, kHop1Split);
     if (g->ws.value_size == 4)
-        hipLaunchKernelGGL(k_hop1_select<float>, dim3(nslots), dim3(256), 0, st, c.qs, sa, slot0,
-                           mode, g->d_row_ptr, g->d_col_idx, g->d_inv_deg_f);
+        hipLaunchKernelGGL(k_hop1_select<float>, grid, dim3(256), 0, st, c.qs, sa, slot0, mode,
+                           g->d_row_ptr, g->d_col_idx, g->d_inv_deg_f, ent);
     else
-        hipLaunchKernelGGL(k_hop1_select<double>, dim3(nslots), dim3(256), 0, st, c.qs, sa, slot0,
-                           mode, g->d_row_ptr, g->d_col_idx, g->d_inv_deg_d);
-    prof_end(g, tok, PK_HOP1, 0.0, 0.0, st);
+        hipLaunchKernelGGL(k_hop1_select<double>, grid, dim3(256), 0, st, c.qs, sa, slot0, mode,
+                           g->d_row_ptr, g->d_col_idx, g->d_inv_deg_d, ent);
+    prof_end_counted(g, tok, PK_HOP1, counter, 8.0 + (double)g->ws.value_size, 0.0, st);
     GEER_HIP(hipGetLastError());
     return GEER_OK;
 }

@@ -117,7 +117,7 @@ extern "C" geer_status geer_autotune(geer_graph *g, int64_t nq, const int32_t *s
             if (w.work_units > 0)
                 tn.ns_per_walk_step = std::min(tn.ns_per_walk_step, 1e6 * w.total_ms / w.work_units);
             const double h2_ms = prof[PK_HOP2_LDS].total_ms + prof[PK_HOP2_SPARSE].total_ms;
-            const double h2_units = prof[PK_HOP2_LDS].work_units;
+            const double h2_units = prof[PK_HOP2_LDS].work_units + prof[PK_HOP2_SPARSE].work_units;
             if (h2_units > 0) tn.ns_per_hop2_unit = std::min(tn.ns_per_hop2_unit, 1e6 * h2_ms / h2_units);
         }
         if (tn.ns_per_walk_step >= 1e300) tn.ns_per_walk_step = 0.05;
