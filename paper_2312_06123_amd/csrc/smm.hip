@@ -761,14 +761,27 @@ __global__ void k_zero_counter(int64_t *c)
     if (threadIdx.x < 2) c[threadIdx.x] = 0;
 }
 
-// Selective hop-1 scatter (modes in geer_internal.h).  Block (k, y) holds
-// four wavefronts; wavefront w takes pair j = y + 16 w of slot k: it decides
-// whether the pair's columns are written (or cleared), scatters both rows
-// and sets the pair's flag, so a flag is never read and reset by different
-// wavefronts.  Every pair of every slot has a wavefront of its own, and a
-// group's hub rows are scattered side by side.  entries (nullable, for the
-// profiler): CSR entries scattered, summed over the launch.
-constexpr int kHop1Split = kMaxPairs / 4;
+// Selective hop-1 scatter (modes in geer_internal.h).  Whether a pair's
+// columns are written (or cleared) depends on its flag and its state only.
+__device__ __forceinline__ bool hop1_need(const QState &qs, int64_t q, int mode,
+                                          const int32_t *__restrict__ row_ptr)
+{
+    if (mode == kHop1Clear) return qs.h1w[q] != 0;
+    if (qs.h1w[q] || qs.lb[q] != 1) return false;
+    if (mode == kHop1Stopped) {
+        // the walk kernel evaluates the vector from LDS rows when both rows fit
+        const int32_t s = qs.s[q], t = qs.t[q];
+        const int32_t ds = row_ptr[s + 1] - row_ptr[s], dt = row_ptr[t + 1] - row_ptr[t];
+        return !qs.active_smm[q] && (ds > kMemberRowMax || dt > kMemberRowMax);
+    }
+    return qs.active_smm[q] != 0;
+}
+
+// The gridDim.y blocks of a slot share every selected pair's two rows: each
+// of their wavefronts takes every (4 gridDim.y)-th run of 64 entries, so a hub
+// row of 4e5 entries is scattered by hundreds of wavefronts at once.  The
+// flags are only read here; k_hop1_flags updates them afterwards.  entries
+// (nullable, for the profiler): CSR entries scattered, summed over the launch.
 
 template <class T>
 __global__ __launch_bounds__(256) void k_hop1_select(QState qs, SlotArgs sa, int slot0, int mode,
@@ -779,48 +792,49 @@ __global__ __launch_bounds__(256) void k_hop1_select(QState qs, SlotArgs sa, int
 {
     const int k = slot0 + (int)blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int j = (int)blockIdx.y + kHop1Split * wave;
-    if (j >= slot_nb(sa, k)) return;
-    const int64_t q = qs.ord[slot_q0(sa, k) + j];
-    const int32_t s = qs.s[q], t = qs.t[q];
-    bool need;
-    if (mode == kHop1Clear) {
-        need = qs.h1w[q] != 0;
-    } else if (qs.h1w[q] || qs.lb[q] != 1) {
-        need = false;
-    } else if (mode == kHop1Stopped) {
-        // the walk kernel evaluates the vector from LDS rows when both rows fit
-        const int32_t ds = row_ptr[s + 1] - row_ptr[s], dt = row_ptr[t + 1] - row_ptr[t];
-        need = !qs.active_smm[q] && (ds > kMemberRowMax || dt > kMemberRowMax);
-    } else {
-        need = qs.active_smm[q] != 0;
-    }
-    if (!need) return;
+    const int nb = slot_nb(sa, k);
+    const int64_t q0 = slot_q0(sa, k);
+    const bool need = lane < nb && hop1_need(qs, qs.ord[q0 + lane], mode, row_ptr);
+    uint64_t m = __ballot(need);
+    const int gw = (int)blockIdx.y * 4 + wave, nw = (int)gridDim.y * 4;
     T *h1 = slot_buf<T>(sa, k, 0);
     uint32_t *h1_bits = slot_bits(sa, k, 0);
     int64_t cnt = 0;
-    for (int side = 0; side < 2; ++side) {
-        const int c = 2 * j + side;
-        const int32_t u = side ? t : s;
-        const uint32_t bit = 1u << (c & 31);
-        const int32_t b = row_ptr[u], e1 = row_ptr[u + 1];
-        cnt += e1 - b;
-        for (int32_t e = b + lane; e < e1; e += 64) {
-            const int32_t v = col_idx[e];
-            uint32_t *bw = h1_bits + (size_t)v * kBitWords + (c >> 5);
-            if (mode == kHop1Clear) {
-                h1[(size_t)v * kCols + c] = T(0);
-                atomicAnd(bw, ~bit);
-            } else {
-                h1[(size_t)v * kCols + c] = inv_deg[v];
-                atomicOr(bw, bit);
+    while (m) {
+        const int j = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        const int64_t q = qs.ord[q0 + j];
+        for (int side = 0; side < 2; ++side) {
+            const int c = 2 * j + side;
+            const int32_t u = side ? qs.t[q] : qs.s[q];
+            const uint32_t bit = 1u << (c & 31);
+            const int32_t b = row_ptr[u], e1 = row_ptr[u + 1];
+            cnt += e1 - b;
+            for (int32_t e = b + gw * 64 + lane; e < e1; e += nw * 64) {
+                const int32_t v = col_idx[e];
+                uint32_t *bw = h1_bits + (size_t)v * kBitWords + (c >> 5);
+                if (mode == kHop1Clear) {
+                    h1[(size_t)v * kCols + c] = T(0);
+                    atomicAnd(bw, ~bit);
+                } else {
+                    h1[(size_t)v * kCols + c] = inv_deg[v];
+                    atomicOr(bw, bit);
+                }
             }
         }
     }
-    if (lane == 0) {
-        qs.h1w[q] = mode == kHop1Clear ? 0 : 1;
-        if (entries) atomicAdd(entries, (unsigned long long)cnt);
-    }
+    if (entries && gw == 0 && lane == 0 && cnt) atomicAdd(entries, (unsigned long long)cnt);
+}
+
+// The flags of the pairs k_hop1_select just wrote (set) or cleared (reset).
+__global__ __launch_bounds__(64) void k_hop1_flags(QState qs, SlotArgs sa, int slot0, int mode,
+                                                   const int32_t *__restrict__ row_ptr)
+{
+    const int k = slot0 + (int)blockIdx.x;
+    const int j = threadIdx.x;
+    if (j >= slot_nb(sa, k)) return;
+    const int64_t q = qs.ord[slot_q0(sa, k) + j];
+    if (hop1_need(qs, q, mode, row_ptr)) qs.h1w[q] = mode == kHop1Clear ? 0 : 1;
 }
 
 geer_status launch_hop1_select(geer_graph *g, const QueryCtx &c, const SlotArgs &sa, int slot0,
@@ -834,13 +848,16 @@ geer_status launch_hop1_select(geer_graph *g, const QueryCtx &c, const SlotArgs 
     int tok = prof_begin(g, st);
     unsigned long long *ent = reinterpret_cast<unsigned long long *>(d_cnt);
     if (d_cnt) hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, st, d_cnt);
-    const dim3 grid(nslots, kHop1Split);
+    // about 2048 blocks in all (8 per CU), at least 16 per slot
+    const dim3 grid(nslots, std::max(16, std::min(512, 2048 / nslots)));
     if (g->ws.value_size == 4)
         hipLaunchKernelGGL(k_hop1_select<float>, grid, dim3(256), 0, st, c.qs, sa, slot0, mode,
                            g->d_row_ptr, g->d_col_idx, g->d_inv_deg_f, ent);
     else
         hipLaunchKernelGGL(k_hop1_select<double>, grid, dim3(256), 0, st, c.qs, sa, slot0, mode,
                            g->d_row_ptr, g->d_col_idx, g->d_inv_deg_d, ent);
+    GEER_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_hop1_flags, dim3(nslots), dim3(64), 0, st, c.qs, sa, slot0, mode, g->d_row_ptr);
     prof_end_counted(g, tok, PK_HOP1, counter, 8.0 + (double)g->ws.value_size, 0.0, st);
     GEER_HIP(hipGetLastError());
     return GEER_OK;
