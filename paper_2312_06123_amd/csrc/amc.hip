@@ -33,13 +33,14 @@ __device__ __forceinline__ bool one_hop_from_graph(int32_t lb, int32_t ds, int32
 // plan: chunk prefix sums for batch `round` of the active queries of a group
 // ----------------------------------------------------------------------------
 
-// sticky (nullable): a fixed plan's overflow word; once set, no chunk is planned.
+// sticky (nullable): a fixed plan's overflow word.  Once it is set no chunk
+// is planned; a round whose chunks exceed cap sets it (bit 0) and plans none.
 __global__ __launch_bounds__(1024) void k_amc_plan(QState qs, int64_t q0, int nq, int round,
                                                    int64_t *__restrict__ chunk_off,
                                                    int64_t *__restrict__ total,
                                                    int64_t *__restrict__ steps,
                                                    const int32_t *__restrict__ row_ptr,
-                                                   const int64_t *__restrict__ sticky)
+                                                   int64_t cap, int64_t *__restrict__ sticky)
 {
     __shared__ int64_t s_sum[1024];
     __shared__ unsigned long long s_steps, s_vsteps;
@@ -84,6 +85,10 @@ __global__ __launch_bounds__(1024) void k_amc_plan(QState qs, int64_t q0, int nq
     if (tid == 1023) {
         chunk_off[nq] = s_sum[1023];
         *total = s_sum[1023];
+        if (sticky && s_sum[1023] > cap) {
+            *sticky |= 1;
+            *total = 0;
+        }
         steps[0] = (int64_t)s_steps;
         steps[1] = (int64_t)s_vsteps;
     }
@@ -93,10 +98,10 @@ __global__ __launch_bounds__(1024) void k_amc_plan(QState qs, int64_t q0, int nq
 // batch is its last (eta_1 2^(tau_q - 1)), so the sum of those chunk counts
 // bounds every round's total.  out: [0] the bound, [1] overflow flag (a batch
 // of 2^32 walk pairs or more), [2] the largest per-pair batch count.
-// With a fixed plan, sticky (nullable) records a bound above cap (bit 0) or
-// a too large batch (bit 1) for the whole call.
+// With a fixed plan, sticky (nullable) records a too large batch (bit 1)
+// for the whole call.
 __global__ __launch_bounds__(1024) void k_amc_bound(QState qs, int64_t q0, int nq,
-                                                    int64_t *__restrict__ out, int64_t cap,
+                                                    int64_t *__restrict__ out,
                                                     int64_t *__restrict__ sticky)
 {
     __shared__ unsigned long long s_chunks;
@@ -131,10 +136,7 @@ __global__ __launch_bounds__(1024) void k_amc_bound(QState qs, int64_t q0, int n
         out[0] = (int64_t)s_chunks;
         out[1] = s_over;
         out[2] = s_tau;
-        if (sticky) {
-            if (s_over) *sticky |= 2;
-            else if ((int64_t)s_chunks > cap) *sticky |= 1;
-        }
+        if (sticky && s_over) *sticky |= 2;
     }
 }
 
@@ -301,8 +303,9 @@ __global__ __launch_bounds__(256) void k_walk(QState qs, int64_t q0, int nq, int
 __global__ __launch_bounds__(256) void k_amc_stop(QState qs, int64_t q0, int nq, int round,
                                                   const int64_t *__restrict__ chunk_off,
                                                   const double2 *__restrict__ zpart, int32_t tau,
-                                                  double delta)
+                                                  double delta, const int64_t *__restrict__ sticky)
 {
+    if (sticky && *sticky) return;  // a fixed plan overflowed: the call fails
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= nq) return;
@@ -360,9 +363,9 @@ geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hip
     // once per group and the rounds then run without host synchronisation
     // (rounds in which no pair is left launch empty grids).  A fixed plan
     // reads nothing: it runs its given rounds on a full grid over the
-    // reserved partials, and the bound kernel flags a group that would not fit.
-    hipLaunchKernelGGL(k_amc_bound, dim3(1), dim3(1024), 0, st, c.qs, grp.q0, nq, d_bound,
-                       grp.zpart_cap, grp.fixed_plan ? grp.sticky : nullptr);
+    // reserved partials, and a round that would not fit sets the overflow word.
+    int64_t *sticky = grp.fixed_plan ? grp.sticky : nullptr;
+    hipLaunchKernelGGL(k_amc_bound, dim3(1), dim3(1024), 0, st, c.qs, grp.q0, nq, d_bound, sticky);
     GEER_HIP(hipGetLastError());
     int64_t bound = 0;
     int rounds = 0;
@@ -406,8 +409,7 @@ geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hip
         int64_t *d_steps = ext ? nullptr : prof_counter(g, &counter);
         if (!d_steps) d_steps = misc + 10;
         hipLaunchKernelGGL(k_amc_plan, dim3(1), dim3(1024), 0, st, c.qs, grp.q0, nq, round,
-                           chunk_off, d_total, d_steps, g->d_row_ptr,
-                           grp.fixed_plan ? grp.sticky : nullptr);
+                           chunk_off, d_total, d_steps, g->d_row_ptr, grp.zpart_cap, sticky);
         GEER_HIP(hipGetLastError());
         for (int part = 0; part < kWalkParts; ++part) {
             int tok = ext ? -1 : prof_begin(g, st);
@@ -438,7 +440,7 @@ geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hip
                                   2.0 * grp.value_size, st);
         }
         hipLaunchKernelGGL(k_amc_stop, dim3((nq + 3) / 4), dim3(256), 0, st, c.qs, grp.q0, nq,
-                           round, chunk_off, zp, c.tau, c.delta);
+                           round, chunk_off, zp, c.tau, c.delta, sticky);
         GEER_HIP(hipGetLastError());
     }
     return GEER_OK;

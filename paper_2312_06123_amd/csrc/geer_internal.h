@@ -426,8 +426,9 @@ struct AmcGroup {
     int vstride = kCols;  // values per node in the vector buffer (kCols, or 2 for one pair)
     // fixed plan (no host read; capturable): run exactly `rounds` rounds on a
     // full persistent grid with the chunk partials in the reserved zpart
-    // buffer of zpart_cap entries; a group needing more sets bit 0 of
-    // *sticky (a batch of 2^32 walk pairs or more: bit 1) and walks nothing
+    // buffer of zpart_cap entries; a round needing more sets bit 0 of
+    // *sticky (a batch of 2^32 walk pairs or more: bit 1), after which no
+    // round walks or updates anything
     bool fixed_plan = false;
     int rounds = 0;
     int64_t zpart_cap = 0;

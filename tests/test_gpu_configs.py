@@ -5,9 +5,11 @@
     decisions agree on >= 99% of pairs and the answers there to 1e-9;
   * R-MAT scale 22 (a = 0.57, b = c = 0.19), 100,000 pairs (half uniform,
     half degree-proportional), per-pair eps drawn from {0.02, 0.05, 0.1},
-    autotuned tile: stratified sample checked against the exact resistance
-    (|r' - r| <= eps, 240 pairs) and replayed by the checker; the graph's bit widths
-    exceed 64, so the walks run on 16-byte records;
+    autotuned tile: the greedy schedule, and the learned one both launched
+    directly and captured in one hipGraph (bit-identical); stratified samples
+    checked against the exact resistance (|r' - r| <= eps, 264 pairs) and
+    replayed by the checker; the graph's bit widths exceed 64, so the walks
+    run on 16-byte records;
   * the learned checkpoint on a fresh Chung-Lu graph (n = 2 * 10^6, the 1M
     configuration's parameters), 50,000 uniform pairs, eps = 0.05: the model
     applies to most pairs, sampled answers are within eps of the exact
@@ -68,11 +70,18 @@ def rmat22_run():
     s = np.concatenate([su, sd])
     t = np.concatenate([tu, td])
     eps = np.random.default_rng(2203).choice(np.array([0.02, 0.05, 0.1]), nq)
+    model = G.Model(path=os.path.join(ROOT, "paper_2312_06123_amd", "data", "scheduler.geermlp"))
+    learned = {}
     with G.Graph(g.n, g.row_ptr32(), g.col_idx) as gg:
         lam = G.geer_graph_compute_lambda(gg.handle, 400, 1e-8, 7)
         ts, tt = I.uniform_pairs(g.n, 1024, 2303)
         G.geer_autotune(gg.handle, ts, tt, 0.05)
         r, st = G.geer_query(gg.handle, s, t, eps, G.geer_params_default(seed=3003), stats=True)
+        for name, flags in (("direct", 0), ("graph", G.GEER_FLAG_GRAPH_LAUNCH)):
+            p = G.geer_params_default(seed=3303, schedule=G.GEER_SCHEDULE_LEARNED,
+                                      model=model.handle.value, flags=flags)
+            learned[name] = G.geer_query(gg.handle, s, t, eps, p, stats=True)
+    model.close()
     # stratified samples per (eps, pair kind): 4 pairs each replayed by the
     # checker, 40 further pairs each checked against the exact resistance
     rng = np.random.default_rng(0)
@@ -83,18 +92,21 @@ def rmat22_run():
             pick = rng.choice(idx, 44, replace=False)
             sample.extend(pick[:4].tolist())
             cover.extend(pick[4:].tolist())
-    return g, s, t, eps, lam, r, st, np.array(sample), np.array(cover)
+    idx = np.concatenate([sample, cover])
+    ex, _ = oracle.exact_cg(g.row_ptr, g.col_idx, s[idx], t[idx], tol=1e-10)
+    exact = dict(zip(idx.tolist(), ex.tolist()))
+    return g, s, t, eps, lam, r, st, np.array(sample), np.array(cover), learned, exact
 
 
 def test_rmat22_coverage_on_stratified_sample(rmat22_run):
     # Definition 2.2: |r' - r| <= eps with probability >= 1 - delta = 0.99;
-    # 240 pairs (40 per eps and pair kind) against the exact resistance
-    g, s, t, eps, lam, r, st, sample, cover = rmat22_run
+    # 264 pairs (44 per eps and pair kind) against the exact resistance
+    g, s, t, eps, lam, r, st, sample, cover, learned, exact = rmat22_run
     deg = g.degrees()
     assert deg.max() > 100_000  # hub rows span hundreds of segments
     assert np.all(np.isfinite(r))
     idx = np.concatenate([sample, cover])
-    ex, _ = oracle.exact_cg(g.row_ptr, g.col_idx, s[idx], t[idx], tol=1e-10)
+    ex = np.array([exact[i] for i in idx.tolist()])
     fails = np.abs(r[idx] - ex) > eps[idx]
     print(f"[coverage] rmat22: {len(idx) - fails.sum()}/{len(idx)} within eps; "
           f"max |r' - r| / eps = {np.max(np.abs(r[idx] - ex) / eps[idx]):.3f}", flush=True)
@@ -103,11 +115,35 @@ def test_rmat22_coverage_on_stratified_sample(rmat22_run):
 
 
 def test_rmat22_replay_on_sample(rmat22_run):
-    g, s, t, eps, lam, r, st, sample, cover = rmat22_run
+    g, s, t, eps, lam, r, st, sample, cover, learned, exact = rmat22_run
     ro, sto = oracle.geer(g.row_ptr, g.col_idx, s[sample], t[sample], eps[sample], lam, seed=3003,
                           qid=sample)
     parity.compare(g, s[sample], t[sample], eps[sample], lam, st[sample], sto, tau=5, seed=3003,
                    qid=sample, label="rmat22 greedy")
+
+
+def test_rmat22_learned_graph_launch(rmat22_run):
+    # the learned schedule with its known-depth groups captured in one hipGraph:
+    # bit-identical to the direct launches, within eps of the exact resistance
+    # on the stratified sample, and equal to the checker's run at the same
+    # (l_b, tau) on the replay sample
+    g, s, t, eps, lam, r, st, sample, cover, learned, exact = rmat22_run
+    (rd, std), (rg, stg) = learned["direct"], learned["graph"]
+    assert np.array_equal(rd, rg)
+    for f in std.dtype.names:
+        assert np.array_equal(std[f], stg[f]), f
+    print(f"[graph] rmat22 learned: fallback {std['fallback'].mean():.4f}, mean l_b {std['ell_b'].mean():.2f}",
+          flush=True)
+    idx = np.concatenate([sample, cover])
+    ex = np.array([exact[i] for i in idx.tolist()])
+    fails = np.abs(rg[idx] - ex) > eps[idx]
+    print(f"[coverage] rmat22 learned: {len(idx) - fails.sum()}/{len(idx)} within eps", flush=True)
+    assert fails.sum() <= 0.01 * len(idx)
+    ro, sto = oracle.geer(g.row_ptr, g.col_idx, s[sample], t[sample], eps[sample], lam, seed=3303,
+                          schedule="fixed", fixed_lb=stg["ell_b"][sample], qid=sample,
+                          tau_per_pair=stg["tau"][sample])
+    parity.compare(g, s[sample], t[sample], eps[sample], lam, stg[sample], sto, tau=None,
+                   tau_per_pair=stg["tau"][sample], seed=3303, qid=sample, label="rmat22 learned graph")
 
 
 # ---------------------------------------------------------------------------

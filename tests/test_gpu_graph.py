@@ -125,17 +125,17 @@ def test_graph_round_beyond_reserved_partials_is_clean_oom():
     s, t = I.uniform_pairs(g.n, 64, 55)
     eps, tau, delta = 2e-4, 5, 0.01
     deg = g.degrees()
-    # the checker's FP64 schedule quantities at depth 1: the group's last
-    # batches need far more chunk partials than the 2^24 reserved, while no
-    # single batch reaches 2^32 walk pairs (that is another error)
+    # the checker's FP64 schedule quantities at depth 1: the group's first
+    # round already needs more chunk partials than the 2^24 reserved, while
+    # no single batch reaches 2^32 walk pairs (that is another error)
     chunks, largest = 0, 0
     for j in range(len(s)):
         x, y, _, _, _ = oracle.smm_vectors(g.row_ptr, g.col_idx, int(s[j]), int(t[j]), 1)
         lf = oracle.ell(deg[s[j]], deg[t[j]], eps, lam) - 1
         psi = oracle.psi(lf, *oracle.top2(x), *oracle.top2(y), float(deg[s[j]]), float(deg[t[j]]))
-        last = int(np.ceil(oracle.eta_star(psi, eps, tau, delta) / 2 ** (tau - 1))) << (tau - 1)
-        chunks += -(-last // 32)
-        largest = max(largest, last)
+        eta1 = int(np.ceil(oracle.eta_star(psi, eps, tau, delta) / 2 ** (tau - 1)))
+        chunks += -(-eta1 // 32)
+        largest = max(largest, eta1 << (tau - 1))
     assert chunks > 2 * 2 ** 24 and largest < 2 ** 31
     depth = np.ones(len(s), dtype=np.int32)
     with G.Graph(g.n, g.row_ptr32(), g.col_idx, lam=lam) as gg:
