@@ -161,11 +161,17 @@ def main(argv=None):
     ap.add_argument("--scale", type=float, default=2.0, help="multiplies every graph's pair count")
     ap.add_argument("--steps", type=int, default=60000)
     ap.add_argument("--report", default=None)
+    ap.add_argument("--graphs", choices=["all", "er"], default="all",
+                    help="all: the five training graphs; er: only the Erdos-Renyi n = 10^4 graph, "
+                         "12,500 uniform pairs at eps 0.05 (200,000 GEER runs)")
     a = ap.parse_args(argv)
     rng = np.random.default_rng(4)
     parts = []
     runs_total = 0
-    for make, nq, n_edge, n_deg, eps_choices, seed in training_graphs(a.scale):
+    graphs = training_graphs(a.scale)
+    if a.graphs == "er":
+        graphs = [(graphs[0][0], 12_500, 0, 0, (0.05,), graphs[0][5])]
+    for make, nq, n_edge, n_deg, eps_choices, seed in graphs:
         g = make()
         parts.append(graph_runs(g, nq, n_edge, n_deg, eps_choices, seed, rng))
         runs_total += (nq + n_edge + n_deg) * len(DEPTHS) * len(TAUS)
