@@ -92,7 +92,7 @@ struct Workspace {
     DevBuf part;      // per-block column statistics (max1, max2 as double; degree sums)
     DevBuf segbuf;    // heavy-row segment partial sums (values + bits)
     DevBuf colstat;   // per slot: per-column reduced statistics of the current hop
-    DevBuf hpart;     // per slot: hop-2 partial column statistics (kPushSplit rows)
+    DevBuf hpart;     // per slot: hop-2 partial column statistics (kPushSplitMax rows)
     DevBuf qstate;    // QState arrays
     DevBuf chunk_off; // AMC: chunk prefix sums per group query
     DevBuf zpart;     // AMC: per-chunk (sum Z, sum Z^2)
@@ -311,7 +311,10 @@ __host__ __device__ inline double bernstein_of(double nz, double var, double psi
 // sorted row of s gives the same value as the random read of the buffer.
 constexpr int32_t kMemberRowMax = 256;
 
-constexpr int kPushSplit = 8;       // blocks per column of the global sparse hop 2
+// blocks per column of the global sparse hop 2: at least kPushSplit, up to
+// kPushSplitMax when few columns take that path (hub columns)
+constexpr int kPushSplit = 8;
+constexpr int kPushSplitMax = 64;
 constexpr double kHop2UnitBytes = 12.0;  // profiler: 4-byte index + 8-byte accumulator per pushed entry
 constexpr int kHashLoadMax = 9830;  // columns with more hop-2 work use the global path
 
@@ -329,7 +332,7 @@ struct SlotArgs {
     int64_t buf_elems;    // n * kCols
     int64_t buf_words;    // n * kBitWords
     double *cs;           // per slot: m1[kCols], m2[kCols], sd[kCols] (int64)
-    double *hpart;        // per slot: m1, m2, sd, each kPushSplit x kCols
+    double *hpart;        // per slot: m1, m2, sd, each kPushSplitMax x kCols
     uint64_t *meta;       // [0,G) active masks, [G,2G) hop-2 masks, [2G,6G) hop-2 paths
 };
 
@@ -354,7 +357,7 @@ __host__ __device__ inline uint32_t *slot_bits(const SlotArgs &a, int k, int whi
 __host__ __device__ inline double *slot_cs(const SlotArgs &a, int k) { return a.cs + (size_t)k * 3 * kCols; }
 __host__ __device__ inline double *slot_hpart(const SlotArgs &a, int k)
 {
-    return a.hpart + (size_t)k * 3 * kPushSplit * kCols;
+    return a.hpart + (size_t)k * 3 * kPushSplitMax * kCols;
 }
 
 struct HopArgs {
@@ -402,17 +405,22 @@ geer_status reserve_dense(geer_graph *g, int value_size);
 geer_status launch_epilogue_group(geer_graph *g, const QueryCtx &c, const SlotArgs &sa,
                                   int nslots, int hop, int which, int value_size, hipStream_t st);
 // global-path sparse hop 2, slots [slot0, slot0 + nslots): mode 0 push,
-// 1 convert (+ statistics into the slot's hop-2 partials), 2 clear
+// 1 convert (+ statistics into partial rows [0, split) of the slot's hop-2
+// partials), 2 clear; split blocks per column (kPushSplit..kPushSplitMax)
 geer_status launch_hop2_sparse(geer_graph *g, const QueryCtx &c, const SlotArgs &sa, int slot0,
-                               int nslots, int value_size, int mode, hipStream_t st);
+                               int nslots, int value_size, int mode, int split, hipStream_t st);
+// blocks per column for a global hop-2 pass over `ncols` columns
+int hop2_split(int ncols);
 geer_status launch_zero(geer_graph *g, void *p, size_t bytes, hipStream_t st);
 // make at least min(want, what fits) slots of hop-2 accumulators available;
 // returns the slot count (0 with *err set on failure)
 int ensure_hop2_acc(geer_graph *g, int want, hipStream_t st, geer_status *err);
 geer_status launch_hop2_lds_group(geer_graph *g, const QueryCtx &c, const SlotArgs &sa,
                                   int nslots, int value_size, hipStream_t st);
-// hop-2 partials -> column statistics for the pairs in each slot's hop-2 mask
-geer_status launch_colstat_group(geer_graph *g, const SlotArgs &sa, int nslots, hipStream_t st);
+// hop-2 partials (rows [0, split)) -> column statistics for the pairs in each
+// slot's hop-2 mask
+geer_status launch_colstat_group(geer_graph *g, const SlotArgs &sa, int nslots, int split,
+                                 hipStream_t st);
 // largest and second-largest entry of columns [0, ncols) of a node-major
 // vector buffer with `stride` values per node -> cs_m1[c], cs_m2[c]
 geer_status launch_column_top2(const geer_graph *g, const void *vec, int ncols, int stride,

@@ -93,7 +93,7 @@ geer_status ensure_slots(geer_graph *g, int slots, int value_size)
     }
     if ((int)ws.a_dirty.size() < slots) ws.a_dirty.resize(slots, 0);
     GEER_TRY(ws.colstat.reserve((size_t)std::max(slots, 1) * kCols * (2 * sizeof(double) + sizeof(int64_t))));
-    GEER_TRY(ws.hpart.reserve((size_t)std::max(slots, 1) * 3 * kPushSplit * kCols * sizeof(double)));
+    GEER_TRY(ws.hpart.reserve((size_t)std::max(slots, 1) * 3 * kPushSplitMax * kCols * sizeof(double)));
     return GEER_OK;
 }
 
@@ -182,7 +182,7 @@ static SlotArgs slot_args(geer_graph *g, const SlotView &sv, const SlotMeta &sm,
     a.buf_elems = (int64_t)sv.n * kCols;
     a.buf_words = (int64_t)sv.n * kBitWords;
     a.cs = g->ws.colstat.as<double>() + (size_t)sv.k0 * 3 * kCols;
-    a.hpart = g->ws.hpart.as<double>() + (size_t)sv.k0 * 3 * kPushSplit * kCols;
+    a.hpart = g->ws.hpart.as<double>() + (size_t)sv.k0 * 3 * kPushSplitMax * kCols;
     a.meta = sm.base;
     return a;
 }
@@ -235,6 +235,7 @@ static geer_status run_level(geer_graph *g, const QueryCtx &c, const SlotView &s
         std::vector<uint64_t> words(5 * (size_t)L, 0);  // h2 masks, then paths
         bool any = false, any_lds = false;
         std::vector<char> glob(nbat, 0);
+        int nglob = 0;  // global-path columns of the level
         for (int k = 0; k < nbat; ++k) {
             if (!hm[k]) continue;
             uint64_t m_lds[2] = {0, 0}, m_glob[2] = {0, 0};
@@ -260,6 +261,7 @@ static geer_status run_level(geer_graph *g, const QueryCtx &c, const SlotView &s
             any = true;
             any_lds |= (m_lds[0] | m_lds[1]) != 0;
             glob[k] = (m_glob[0] | m_glob[1]) != 0;
+            nglob += __builtin_popcountll(m_glob[0]) + __builtin_popcountll(m_glob[1]);
             words[k] = hm[k];
             uint64_t *pw = &words[L + 4 * (size_t)k];
             pw[0] = m_lds[0];
@@ -279,7 +281,7 @@ static geer_status run_level(geer_graph *g, const QueryCtx &c, const SlotView &s
                     ws.a_dirty[sv.k0 + k] = 0;
                 }
             GEER_TRY(set_words(sm.h2(0), words.data(), words.size(), c.stream));
-            GEER_TRY(launch_zero(g, sa.hpart, (size_t)nbat * 3 * kPushSplit * kCols * sizeof(double),
+            GEER_TRY(launch_zero(g, sa.hpart, (size_t)nbat * 3 * kPushSplitMax * kCols * sizeof(double),
                                  c.stream));
             if (any_lds) GEER_TRY(launch_hop2_lds_group(g, c, sa, nbat, sv.vs, c.stream));
             int k0 = 0, k1 = -1;  // slots with global-path columns lie in [k0, k1]
@@ -287,17 +289,18 @@ static geer_status run_level(geer_graph *g, const QueryCtx &c, const SlotView &s
                 if (glob[k]) k0 = k;
             for (int k = 0; k < nbat; ++k)
                 if (glob[k]) k1 = k;
+            const int split = hop2_split(nglob);
             if (k1 >= k0) {
                 geer_status err;
                 const int A = ensure_hop2_acc(g, k1 - k0 + 1, c.stream, &err);
                 GEER_TRY(err);
                 for (int a0 = k0; a0 <= k1; a0 += A) {
                     const int na = std::min(A, k1 + 1 - a0);
-                    GEER_TRY(launch_hop2_sparse(g, c, sa, a0, na, sv.vs, 0, c.stream));
-                    GEER_TRY(launch_hop2_sparse(g, c, sa, a0, na, sv.vs, 1, c.stream));
+                    GEER_TRY(launch_hop2_sparse(g, c, sa, a0, na, sv.vs, 0, split, c.stream));
+                    GEER_TRY(launch_hop2_sparse(g, c, sa, a0, na, sv.vs, 1, split, c.stream));
                 }
             }
-            GEER_TRY(launch_colstat_group(g, sa, nbat, c.stream));
+            GEER_TRY(launch_colstat_group(g, sa, nbat, split, c.stream));
             for (int k = 0; k < nbat; ++k)
                 if (sparse[k]) recs[k].hop2_sparse = hm[k];
         }
@@ -330,6 +333,7 @@ static geer_status cleanup_group(geer_graph *g, const QueryCtx &c, const SlotVie
                                  const std::vector<BatchRec> &recs)
 {
     bool h1 = false, h1s = false, h2 = false;
+    int ncols = 0;
     std::vector<uint64_t> words(nbat, 0);
     for (int k = 0; k < nbat; ++k) {
         h1 |= recs[k].hop1;
@@ -338,6 +342,7 @@ static geer_status cleanup_group(geer_graph *g, const QueryCtx &c, const SlotVie
         // before its next sparse use instead
         if (recs[k].hop2_sparse && !g->ws.a_dirty[sv.k0 + k]) {
             words[k] = recs[k].hop2_sparse;
+            ncols += 2 * __builtin_popcountll(words[k]);
             h2 = true;
         }
     }
@@ -345,7 +350,7 @@ static geer_status cleanup_group(geer_graph *g, const QueryCtx &c, const SlotVie
     if (h1s) GEER_TRY(launch_hop1_select(g, c, sa, 0, nbat, kHop1Clear, c.stream));
     if (h2) {
         GEER_TRY(set_words(sm.h2(0), words.data(), words.size(), c.stream));
-        GEER_TRY(launch_hop2_sparse(g, c, sa, 0, nbat, sv.vs, 2, c.stream));
+        GEER_TRY(launch_hop2_sparse(g, c, sa, 0, nbat, sv.vs, 2, hop2_split(ncols), c.stream));
     }
     return GEER_OK;
 }

@@ -583,20 +583,20 @@ __global__ __launch_bounds__(256) void k_colstat_reduce(const double *__restrict
     }
 }
 
-// Hop-2 column statistics of a group: the kPushSplit partial rows of each
+// Hop-2 column statistics of a group: the `split` partial rows of each
 // column of a pair in the slot's hop-2 mask.  One wavefront per (column, slot).
-__global__ __launch_bounds__(64) void k_colstat_group(SlotArgs sa)
+__global__ __launch_bounds__(64) void k_colstat_group(SlotArgs sa, int split)
 {
     const int c = blockIdx.x, k = blockIdx.y, lane = threadIdx.x;
     if (!((sa.meta[sa.G + k] >> (c >> 1)) & 1ull)) return;
     const double *hp = slot_hpart(sa, k);
-    const int64_t *hsd = reinterpret_cast<const int64_t *>(hp + 2 * kPushSplit * kCols);
+    const int64_t *hsd = reinterpret_cast<const int64_t *>(hp + 2 * kPushSplitMax * kCols);
     double a1 = 0.0, a2 = 0.0;
     int64_t sd = 0;
-    if (lane < kPushSplit) {
+    if (lane < split) {
         const size_t o = (size_t)lane * kCols + c;
         a1 = hp[o];
-        a2 = hp[kPushSplit * kCols + o];
+        a2 = hp[kPushSplitMax * kCols + o];
         sd = hsd[o];
     }
     for (int o = 32; o > 0; o >>= 1) {
@@ -1050,23 +1050,27 @@ __device__ __forceinline__ unsigned long long fixed_inv_deg(double inv_d, int sh
 constexpr int kPushChunk = 2048;  // neighbours of u staged in LDS per round
 
 // mode 0: accumulate; mode 1: convert + stats; mode 2: clear the output entries.
-// The work of column c is the concatenation of the rows N(v), v in N(u).  A
-// block stages a chunk of N(u) and the prefix sums of the degrees in LDS and
-// spreads the flattened entries over all of its lanes (and the kPushSplit
-// blocks of the column), so hub rows do not serialise on one wavefront.
+// The work of column c is the concatenation of the rows N(v), v in N(u),
+// shared by the column's `split` blocks.  A block stages a chunk of N(u) and
+// the prefix sums of the degrees in LDS and spreads the chunk's flattened
+// entries over its lanes.  When N(u) has at least `split` chunks, each block
+// takes whole chunks (every split-th); otherwise every block stages every
+// chunk and takes every split-th run of 256 entries.  Either way a hub
+// column is spread over all its blocks, and no result depends on the split
+// (sums are exact integers, each entry is converted by its first visitor).
 template <class T, int MODE>
 __global__ __launch_bounds__(256) void k_hop2_sparse(
     QState qs, SlotArgs sa, int slot0, const int32_t *__restrict__ row_ptr,
     const int32_t *__restrict__ col_idx, const double *__restrict__ inv_deg_d,
-    unsigned long long *__restrict__ acc, int shift)
+    unsigned long long *__restrict__ acc, int shift, int split)
 {
     __shared__ int32_t s_v[kPushChunk];
     __shared__ int32_t s_beg[kPushChunk];
     __shared__ int32_t s_pre[kPushChunk + 1];
     __shared__ int32_t s_tmp[256];
     const int c = blockIdx.x;
-    const int slot = slot0 + (int)blockIdx.y / kPushSplit;
-    const int k = (int)blockIdx.y % kPushSplit;  // this block's share of the column
+    const int slot = slot0 + (int)blockIdx.y / split;
+    const int k = (int)blockIdx.y % split;  // this block's share of the column
     const int j = c >> 1;
     // modes 0/1: per-column global-path mask (two words); mode 2: the pair mask
     const uint64_t *mask_p = MODE == 2 ? sa.meta + sa.G + slot : sa.meta + 2 * sa.G + 4 * slot + 2;
@@ -1083,7 +1087,10 @@ __global__ __launch_bounds__(256) void k_hop2_sparse(
         const int32_t u = (c & 1) ? qs.t[q] : qs.s[q];
         const int32_t b0 = row_ptr[u], du = row_ptr[u + 1] - b0;
         const uint32_t bit = 1u << (c & 31);
-        for (int32_t base = 0; base < du; base += kPushChunk) {
+        const int32_t nch = (du + kPushChunk - 1) / kPushChunk;
+        const bool by_chunk = nch >= split;
+        for (int32_t ch = by_chunk ? k : 0; ch < nch; ch += by_chunk ? split : 1) {
+            const int32_t base = ch * kPushChunk;
             const int cnt = min(kPushChunk, du - base);
             // stage v, its row start and degree; 256-thread scan of the degrees
             const int per = (cnt + 255) / 256;
@@ -1113,7 +1120,9 @@ __global__ __launch_bounds__(256) void k_hop2_sparse(
             if (tid == 255) s_pre[cnt] = s_tmp[255];
             __syncthreads();
             const int32_t total = s_pre[cnt];
-            for (int32_t p = k * 256 + tid; p < total; p += kPushSplit * 256) {
+            const int32_t p0 = by_chunk ? tid : k * 256 + tid;
+            const int32_t pstep = by_chunk ? 256 : split * 256;
+            for (int32_t p = p0; p < total; p += pstep) {
                 // entry p lies in row s_v[i] with s_pre[i] <= p < s_pre[i+1]
                 int lo = 0, hi = cnt;
                 while (hi - lo > 1) {
@@ -1171,8 +1180,8 @@ __global__ __launch_bounds__(256) void k_hop2_sparse(
         double *hp = slot_hpart(sa, slot);
         const size_t o = (size_t)k * kCols + c;
         hp[o] = a1;
-        hp[kPushSplit * kCols + o] = a2;
-        reinterpret_cast<int64_t *>(hp + 2 * kPushSplit * kCols)[o] = t;
+        hp[kPushSplitMax * kCols + o] = a2;
+        reinterpret_cast<int64_t *>(hp + 2 * kPushSplitMax * kCols)[o] = t;
     }
 }
 
@@ -1305,8 +1314,8 @@ __global__ __launch_bounds__(512) void k_hop2_lds(QState qs, SlotArgs sa,
         // partial row 0 (the other rows of an LDS-path column stay zero)
         double *hp = slot_hpart(sa, slot);
         hp[c] = a1;
-        hp[kPushSplit * kCols + c] = a2;
-        reinterpret_cast<int64_t *>(hp + 2 * kPushSplit * kCols)[c] = t;
+        hp[kPushSplitMax * kCols + c] = a2;
+        reinterpret_cast<int64_t *>(hp + 2 * kPushSplitMax * kCols)[c] = t;
     }
 }
 
@@ -1327,20 +1336,27 @@ geer_status launch_hop2_lds_group(geer_graph *g, const QueryCtx &c, const SlotAr
     return GEER_OK;
 }
 
+int hop2_split(int ncols)
+{
+    // about 2048 blocks over the columns of the pass
+    return std::max(kPushSplit, std::min(kPushSplitMax, 2048 / std::max(ncols, 1)));
+}
+
 geer_status launch_hop2_sparse(geer_graph *g, const QueryCtx &c, const SlotArgs &sa, int slot0,
-                               int nslots, int value_size, int mode, hipStream_t st)
+                               int nslots, int value_size, int mode, int split, hipStream_t st)
 {
     if (nslots <= 0) return GEER_OK;
+    if (split < 1 || split > kPushSplitMax) return fail(GEER_E_INVALID_ARG, "hop-2 split out of range");
     Workspace &ws = g->ws;
     // push and convert use accumulator block (slot - slot0) of each slot
     if (mode != 2 && nslots > ws.acc_slots)
         return fail(GEER_E_INVALID_ARG, "hop-2 push covers more slots than accumulators");
     unsigned long long *acc = ws.acc.as<unsigned long long>();
-    const dim3 grid(kCols, kPushSplit * nslots);
+    const dim3 grid(kCols, split * nslots);
     int tok = prof_begin(g, st);
 #define GEER_PUSH(T_, M_)                                                                      \
     hipLaunchKernelGGL((k_hop2_sparse<T_, M_>), grid, dim3(256), 0, st, c.qs, sa, slot0,        \
-                       g->d_row_ptr, g->d_col_idx, g->d_inv_deg_d, acc, g->fx_shift)
+                       g->d_row_ptr, g->d_col_idx, g->d_inv_deg_d, acc, g->fx_shift, split)
     if (value_size == 4) {
         if (mode == 0) GEER_PUSH(float, 0);
         else if (mode == 1) GEER_PUSH(float, 1);
@@ -1376,11 +1392,12 @@ int ensure_hop2_acc(geer_graph *g, int want, hipStream_t st, geer_status *err)
     return slots;
 }
 
-geer_status launch_colstat_group(geer_graph *g, const SlotArgs &sa, int nslots, hipStream_t st)
+geer_status launch_colstat_group(geer_graph *g, const SlotArgs &sa, int nslots, int split,
+                                 hipStream_t st)
 {
     if (nslots <= 0) return GEER_OK;
     int tok = prof_begin(g, st);
-    hipLaunchKernelGGL(k_colstat_group, dim3(kCols, nslots), dim3(64), 0, st, sa);
+    hipLaunchKernelGGL(k_colstat_group, dim3(kCols, nslots), dim3(64), 0, st, sa, split);
     prof_end(g, tok, PK_COLSTAT, 0.0, 0.0, st);
     GEER_HIP(hipGetLastError());
     return GEER_OK;
