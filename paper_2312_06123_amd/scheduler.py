@@ -37,7 +37,7 @@ from . import geer as G
 from . import inputs as I
 
 DEPTHS = (1, 2, 3, 4)
-TAUS = (2, 3, 5, 8)
+TAUS = (2, 3, 4, 5, 6, 8)
 EPS_REF = 1e-3
 
 
@@ -45,11 +45,11 @@ def log(msg):
     print(f"[scheduler] {msg}", file=sys.stderr, flush=True)
 
 
-def sweep(gg, s, t, eps, seed=7):
+def sweep(gg, s, t, eps, seed=7, taus=None):
     """Run every fixed (l_b, tau) on the pairs -> dict (lb, tau) -> stats."""
     out = {}
     for lb in DEPTHS:
-        for tau in TAUS:
+        for tau in (taus or TAUS):
             p = G.geer_params_default(seed=seed, tau=tau)
             r, st = G.geer_query(gg.handle, s, t, eps, p, stats=True, fixed_ell_b=lb)
             out[(lb, tau)] = (r, st)
@@ -97,7 +97,7 @@ def label(feats, runs, r_ref, rng, n_rho=4):
     return np.concatenate(Xs), np.concatenate(Ys), np.concatenate(Ws)
 
 
-def graph_runs(g, nq, n_edge, n_deg, eps_choices, seed, rng):
+def graph_runs(g, nq, n_edge, n_deg, eps_choices, seed, rng, taus=None):
     """Features, schedule sweep and reference answers on one training graph:
     ``nq`` uniform pairs, ``n_edge`` pairs that are edges of the graph and
     ``n_deg`` pairs with both endpoints drawn by degree.  Each pair draws its
@@ -115,7 +115,7 @@ def graph_runs(g, nq, n_edge, n_deg, eps_choices, seed, rng):
     with G.Graph(g.n, g.row_ptr32(), g.col_idx) as gg:
         lam = G.geer_graph_compute_lambda(gg.handle, 300, 1e-9, seed)
         t0 = time.time()
-        runs = sweep(gg, s, t, eps, seed)
+        runs = sweep(gg, s, t, eps, seed, taus)
         log(f"{g.name}: {len(runs) * nq} GEER runs in {time.time() - t0:.1f} s (lambda={lam:.4f})")
         r_ref = reference(gg, s, t)
         log(f"  reference answers (SMM only, eps {EPS_REF})")
@@ -161,6 +161,8 @@ def main(argv=None):
     ap.add_argument("--scale", type=float, default=2.0, help="multiplies every graph's pair count")
     ap.add_argument("--steps", type=int, default=60000)
     ap.add_argument("--report", default=None)
+    ap.add_argument("--taus", default=",".join(str(x) for x in TAUS),
+                    help="AMC batch counts of the schedule sweep (comma separated)")
     ap.add_argument("--graphs", choices=["all", "er"], default="all",
                     help="all: the five training graphs; er: only the Erdos-Renyi n = 10^4 graph, "
                          "12,500 uniform pairs at eps 0.05 (200,000 GEER runs)")
@@ -171,10 +173,11 @@ def main(argv=None):
     graphs = training_graphs(a.scale)
     if a.graphs == "er":
         graphs = [(graphs[0][0], 12_500, 0, 0, (0.05,), graphs[0][5])]
+    taus = tuple(int(x) for x in a.taus.split(","))
     for make, nq, n_edge, n_deg, eps_choices, seed in graphs:
         g = make()
-        parts.append(graph_runs(g, nq, n_edge, n_deg, eps_choices, seed, rng))
-        runs_total += (nq + n_edge + n_deg) * len(DEPTHS) * len(TAUS)
+        parts.append(graph_runs(g, nq, n_edge, n_deg, eps_choices, seed, rng, taus))
+        runs_total += (nq + n_edge + n_deg) * len(DEPTHS) * len(taus)
     X = np.concatenate([p[0] for p in parts])
     Y = np.concatenate([p[1] for p in parts])
     W = np.concatenate([p[2] for p in parts])
