@@ -166,21 +166,35 @@ def main(argv=None):
     ap.add_argument("--graphs", choices=["all", "er"], default="all",
                     help="all: the five training graphs; er: only the Erdos-Renyi n = 10^4 graph, "
                          "12,500 uniform pairs at eps 0.05 (200,000 GEER runs)")
+    ap.add_argument("--w-tau", type=float, default=None,
+                    help="loss weight of the tau output (default: the labelling rule's 0.25)")
+    ap.add_argument("--samples-out", default=None, help="save the labelled samples (.npz)")
+    ap.add_argument("--samples-in", default=None,
+                    help="train on labelled samples saved by --samples-out instead of sweeping")
     a = ap.parse_args(argv)
-    rng = np.random.default_rng(4)
-    parts = []
-    runs_total = 0
-    graphs = training_graphs(a.scale)
-    if a.graphs == "er":
-        graphs = [(graphs[0][0], 12_500, 0, 0, (0.05,), graphs[0][5])]
-    taus = tuple(int(x) for x in a.taus.split(","))
-    for make, nq, n_edge, n_deg, eps_choices, seed in graphs:
-        g = make()
-        parts.append(graph_runs(g, nq, n_edge, n_deg, eps_choices, seed, rng, taus))
-        runs_total += (nq + n_edge + n_deg) * len(DEPTHS) * len(taus)
-    X = np.concatenate([p[0] for p in parts])
-    Y = np.concatenate([p[1] for p in parts])
-    W = np.concatenate([p[2] for p in parts])
+    if a.samples_in:
+        z = np.load(a.samples_in)
+        X, Y, W, runs_total = z["X"], z["Y"], z["W"], int(z["runs"])
+    else:
+        rng = np.random.default_rng(4)
+        parts = []
+        runs_total = 0
+        graphs = training_graphs(a.scale)
+        if a.graphs == "er":
+            graphs = [(graphs[0][0], 12_500, 0, 0, (0.05,), graphs[0][5])]
+        taus = tuple(int(x) for x in a.taus.split(","))
+        for make, nq, n_edge, n_deg, eps_choices, seed in graphs:
+            g = make()
+            parts.append(graph_runs(g, nq, n_edge, n_deg, eps_choices, seed, rng, taus))
+            runs_total += (nq + n_edge + n_deg) * len(DEPTHS) * len(taus)
+        X = np.concatenate([p[0] for p in parts])
+        Y = np.concatenate([p[1] for p in parts])
+        W = np.concatenate([p[2] for p in parts])
+        if a.samples_out:
+            np.savez(a.samples_out, X=X, Y=Y, W=W, runs=runs_total)
+    if a.w_tau is not None:
+        W = W.copy()
+        W[:, 1] = a.w_tau
     log(f"{X.shape[0]} labelled samples from {runs_total} GEER runs")
     t0 = time.time()
     m, losses, _ = train_model(X, Y, W, a.steps)
