@@ -275,11 +275,14 @@ geer_status geer_amc_device_noalloc(geer_graph *g, int32_t s, int32_t t, const v
  * neighbour degrees of s), same for t, log2 of the smallest neighbour degree
  * of s, same for t, edge(s,t), log2(1 + common neighbours),
  * log2(1/(1-lambda)), log2 eps, log2 rho2, log2 rhod (cost ratios of the
- * graph, geer_graph_set_costs). */
-#define GEER_MLP_FEATURES 13
+ * graph, geer_graph_set_costs), log2(max(psi_1, 2^-40) / eps) with psi_1 the
+ * Eq. (Delta-st) bound after one product (l_f = l - 1; max1 = 1/(smallest
+ * neighbour degree), max2 = 1/(second smallest) or 0 when the degree is 1;
+ * psi_1 = 0 when l <= 1). */
+#define GEER_MLP_FEATURES 14
 #define GEER_MLP_HIDDEN 64
 #define GEER_MLP_OUTPUTS 3
-#define GEER_MLP_PARAMS (13 * 64 + 64 + 64 * 64 + 64 + 64 * 3 + 3)
+#define GEER_MLP_PARAMS (14 * 64 + 64 + 64 * 64 + 64 + 64 * 3 + 3)
 
 /* New model with He-uniform weights from `seed` (host memory; device copies
  * are made on first use on the current device). */

@@ -14,7 +14,7 @@ from __future__ import annotations
 
 import numpy as np
 
-F, H, O = 13, 64, 3
+F, H, O = 14, 64, 3
 P = F * H + H + H * H + H + H * O + O
 
 

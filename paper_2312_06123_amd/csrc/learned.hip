@@ -44,8 +44,9 @@ __global__ __launch_bounds__(256) void k_features(
     int64_t nq, const int32_t *__restrict__ s_arr, const int32_t *__restrict__ t_arr,
     const double *__restrict__ eps_arr, const int32_t *__restrict__ ell_arr,
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
-    const int64_t *__restrict__ nbr_work, const int32_t *__restrict__ min_nbr_deg, double lambda,
-    double log_mean_deg, double rho2, double rhod, float *__restrict__ feat)
+    const int64_t *__restrict__ nbr_work, const int32_t *__restrict__ min_nbr_deg,
+    const int32_t *__restrict__ nbr_deg2, double lambda, double log_mean_deg, double rho2,
+    double rhod, float *__restrict__ feat)
 {
     const int lane = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -80,6 +81,18 @@ __global__ __launch_bounds__(256) void k_features(
     f[10] = (float)log2(eps_arr[i]);
     f[11] = (float)log2(rho2);
     f[12] = (float)log2(rhod);
+    // psi of Eq. (Delta-st) after one product, relative to eps: the hop-1
+    // vector of s is 1/d(v) on N(s), so its largest entry is 1/(smallest
+    // neighbour degree) and its second largest 1/(second smallest), 0 when
+    // d(s) = 1; the first AMC batch at l_b = 1 grows as (psi_1 / eps)^2
+    const int32_t lf = ell_arr[i] - 1;
+    double psi1 = 0.0;
+    if (lf > 0) {
+        const int32_t s2 = nbr_deg2[s], t2 = nbr_deg2[t];
+        psi1 = psi_of(lf, 1.0 / min_nbr_deg[s], s2 > 0 ? 1.0 / s2 : 0.0, 1.0 / min_nbr_deg[t],
+                      t2 > 0 ? 1.0 / t2 : 0.0, 1.0 / ds, 1.0 / dt);
+    }
+    f[13] = (float)log2(fmax(psi1, ldexp(1.0, -40)) / eps_arr[i]);
     (void)log_mean_deg;
 }
 
@@ -479,8 +492,8 @@ geer_status launch_learned(geer_graph *g, const QueryCtx &c, const geer_model *m
     int tok = prof_begin(g, st);
     hipLaunchKernelGGL(k_features, dim3((int)((c.nq + 3) / 4)), dim3(256), 0, st, c.nq, c.qs.s,
                        c.qs.t, c.qs.eps, c.qs.ell, g->d_row_ptr, g->d_col_idx, g->d_nbr_work,
-                       g->d_min_nbr_deg, c.lambda, std::log2((double)g->nnz / g->n), g->rho2,
-                       g->rhod, d_feat);
+                       g->d_min_nbr_deg, g->d_nbr_deg2, c.lambda, std::log2((double)g->nnz / g->n),
+                       g->rho2, g->rhod, d_feat);
     prof_end(g, tok, PK_FEATURES, 0.0, 0.0, st);
     GEER_HIP(hipGetLastError());
     tok = prof_begin(g, st);
@@ -665,8 +678,9 @@ geer_status geer_features(geer_graph *g, int64_t nq, const int32_t *s, const int
     GEER_HIP(hipMemcpyAsync(d_t, t, nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
     GEER_HIP(hipMemcpyAsync(d_ell, ell.data(), nq * sizeof(int32_t), hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_features, dim3((int)((nq + 3) / 4)), dim3(256), 0, st, nq, d_s, d_t, d_eps,
-                       d_ell, g->d_row_ptr, g->d_col_idx, g->d_nbr_work, g->d_min_nbr_deg, g->lambda,
-                       std::log2((double)g->nnz / g->n), g->rho2, g->rhod, d_f);
+                       d_ell, g->d_row_ptr, g->d_col_idx, g->d_nbr_work, g->d_min_nbr_deg,
+                       g->d_nbr_deg2, g->lambda, std::log2((double)g->nnz / g->n), g->rho2, g->rhod,
+                       d_f);
     GEER_HIP(hipGetLastError());
     GEER_HIP(hipMemcpyAsync(feat_out, d_f, (size_t)nq * kF * sizeof(float), hipMemcpyDeviceToHost, st));
     GEER_HIP(hipStreamSynchronize(st));

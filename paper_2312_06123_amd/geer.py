@@ -53,10 +53,10 @@ EXPORTED = [
     "geer_amc_device_noalloc",
 ]
 
-MLP_FEATURES = 13
+MLP_FEATURES = 14
 MLP_HIDDEN = 64
 MLP_OUTPUTS = 3
-MLP_PARAMS = 13 * 64 + 64 + 64 * 64 + 64 + 64 * 3 + 3
+MLP_PARAMS = 14 * 64 + 64 + 64 * 64 + 64 + 64 * 3 + 3
 
 
 class GeerError(RuntimeError):

@@ -103,6 +103,15 @@ def test_features_match_definition():
     with G.Graph(g.n, g.row_ptr32(), g.col_idx, lam=lam) as gg:
         G.geer_graph_set_costs(gg.handle, 5.0, 3e5)
         f = G.geer_features(gg.handle, s, t, 0.05)
+    def log_psi1(i):
+        # Eq. (Delta-st) after one product from the checker's hop-1 vectors
+        ell = oracle.ell(deg[s[i]], deg[t[i]], 0.05, lam)
+        if ell <= 1:
+            return np.log2(2.0 ** -40 / 0.05)
+        x, y, _, _, _ = oracle.smm_vectors(g.row_ptr, g.col_idx, int(s[i]), int(t[i]), 1)
+        psi = oracle.psi(ell - 1, *oracle.top2(x), *oracle.top2(y), float(deg[s[i]]), float(deg[t[i]]))
+        return np.log2(psi / 0.05)
+
     for i in range(len(s)):
         ns = g.col_idx[g.row_ptr[s[i]]:g.row_ptr[s[i] + 1]]
         nt = g.col_idx[g.row_ptr[t[i]]:g.row_ptr[t[i] + 1]]
@@ -111,7 +120,7 @@ def test_features_match_definition():
                 np.log2(1 + deg[ns].sum()), np.log2(1 + deg[nt].sum()),
                 np.log2(deg[ns].min()), np.log2(deg[nt].min()),
                 float(t[i] in ns), np.log2(1 + len(np.intersect1d(ns, nt))),
-                np.log2(1 / (1 - lam)), np.log2(0.05), snap(5.0), snap(3e5)]
+                np.log2(1 / (1 - lam)), np.log2(0.05), snap(5.0), snap(3e5), log_psi1(i)]
         assert np.allclose(f[i], np.array(want, dtype=np.float32), rtol=1e-6, atol=1e-6), i
 
 
