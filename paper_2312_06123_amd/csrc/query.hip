@@ -667,6 +667,8 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
         sig.add(col_tile);
         sig.add(n_static);
         sig.add(n_fixed);
+        sig.add(max_hops);
+        sig.add(meta_words);
         sig.add(zcap);
         sig.add(c.tau);
         sig.add(c.delta);
