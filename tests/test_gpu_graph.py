@@ -7,8 +7,9 @@ the column tile.  Covered: FIXED depths over several groups on two slot sets
 (capture, replay, capture again after the inputs change), FP64 vectors, the
 device entry point, LEARNED (the shipped checkpoint, and untrained weights
 with a narrow feature range so that many pairs fall back to the greedy
-switch, whose groups are launched directly after the graph), and the clean
-GEER_E_OOM of a round beyond the reserved chunk partials.
+switch, whose groups are launched directly after the graph), the clean
+GEER_E_OOM of a captured round beyond the reserved chunk partials, while
+direct launches of the same call (chunk bounds read per group) answer it.
 """
 
 import os
@@ -170,3 +171,35 @@ def test_graph_buffers_return_to_the_device(cl_graph):
     print(f"[graph] buffers {used / 1e9:.2f} GB; not returned {(free0 - back) / 1e9:.3f} GB", flush=True)
     assert used > 256 << 20
     assert free0 - back < 64 << 20
+
+
+def test_direct_launches_not_limited_by_reserved_partials():
+    # A captured plan reserves a fixed number of chunk partials; direct
+    # launches read each group's chunk bound and size the partials to it, so
+    # a call whose first round does not fit the captured plan still answers
+    # within eps.
+    g = I.erdos_renyi_path(2000, 10, 101)
+    lam = oracle.lambda_dense(g.row_ptr, g.col_idx)
+    s, t = I.uniform_pairs(g.n, 64, 57)
+    eps, tau, delta = 6e-4, 2, 0.01
+    deg = g.degrees()
+    chunks = 0
+    for j in range(len(s)):
+        x, y, _, _, _ = oracle.smm_vectors(g.row_ptr, g.col_idx, int(s[j]), int(t[j]), 1)
+        lf = oracle.ell(deg[s[j]], deg[t[j]], eps, lam) - 1
+        psi = oracle.psi(lf, *oracle.top2(x), *oracle.top2(y), float(deg[s[j]]), float(deg[t[j]]))
+        chunks += -(-int(np.ceil(oracle.eta_star(psi, eps, tau, delta) / 2 ** (tau - 1))) // 32)
+    assert chunks > 2 ** 24  # the first round does not fit the fixed plan
+    depth = np.ones(len(s), dtype=np.int32)
+    kw = dict(seed=3, schedule=G.GEER_SCHEDULE_FIXED, fixed_ell_b=depth.ctypes.data, tau=tau, delta=delta)
+    exact = oracle.exact_pinv(g.row_ptr, g.col_idx, s, t)
+    with G.Graph(g.n, g.row_ptr32(), g.col_idx, lam=lam) as gg:
+        with pytest.raises(G.GeerError) as e:
+            _run(gg, s, t, eps, True, **kw)
+        assert e.value.status == G.GEER_E_OOM
+        r, st = _run(gg, s, t, eps, False, **kw)
+        err = np.abs(r - exact)
+        print(f"[graph] rerun with bounds: max |err| {err.max():.2e} (eps {eps})", flush=True)
+        assert np.all(err <= eps)
+        assert np.all(st["ell_b"] == 1)
+        assert np.all(st["walk_pairs"] > 0)
