@@ -1,20 +1,25 @@
 """Training pipeline of the learned SMM/AMC scheduler.
 
-The network (13 features -> 64 -> 64 -> 3) predicts, per pair, the SMM depth
+The network (14 features -> 64 -> 64 -> 3) predicts, per pair, the SMM depth
 l_b and the AMC batch count tau that minimise the pair's cost on the GPU, and
 log10 of the resulting absolute error.  Training data comes from GEER runs of
 this library itself:
 
   * every training pair is answered with each fixed schedule (l_b, tau) of a
     small grid (FIXED schedule, per-pair depth clamped to l);
-  * a pair's cost under a schedule, in units of one walk step, is
-        steps + rho2 * W2 * [l_b >= 2] + rhod * max(l_b - 2, 0)
-    where steps = 2 * walk pairs * (l - l_b) is the AMC work, W2 the sparse
-    hop-2 work (neighbour-degree sums of s and t) and rhod the cost of one
-    dense hop per pair of a full batch; rho2 and rhod vary between devices and
-    graphs, so each pair is labelled under several sampled (rho2, rhod) and
-    the two ratios are inputs of the network (the autotuner measures them on
-    the graph the model is used on);
+  * a pair's cost under a schedule, in units of one walk step that reads no
+    vector, is
+        steps * (1 + (rho_v - 1) * V) + rho2 * W2 * [l_b >= 2] + rhod * max(l_b - 2, 0)
+    where steps = 2 * walk pairs * (l - l_b) is the AMC work, V = 1 when each
+    step also reads the pair's two vector values at the new node (l_b >= 2,
+    or l_b = 1 with a row of s or t longer than the walk kernel evaluates from
+    the graph), rho_v the cost of such a step relative to one that reads only
+    its walk record (a property of the device: --rho-v), W2 the sparse hop-2
+    work (neighbour-degree sums of s and t) and rhod the cost of one dense hop
+    per pair of a full batch; rho2 and rhod vary between graphs, so each pair
+    is labelled under several sampled (rho2, rhod) and the two ratios are
+    inputs of the network (the autotuner measures them on the graph the model
+    is used on);
   * the label is the cheapest schedule; its error is measured against the
     library's own SMM-only answer at a tight eps (Theorem 3.1 bounds that
     reference's truncation error by eps_ref / 2).
@@ -39,6 +44,17 @@ from . import inputs as I
 DEPTHS = (1, 2, 3, 4)
 TAUS = (2, 3, 4, 5, 6, 8)
 EPS_REF = 1e-3
+# rows of s and t up to this length: the walk kernel evaluates the one-hop
+# vectors from the graph (no vector read per step)
+MEMBER_ROW_MAX = 256
+# Weight of a walk step that reads the pair's vector values, relative to one
+# that reads only its walk record.  Such a step fetches 1.8x the lines on
+# MI355X, yet labels weighted 2 or 3 trained models that were no faster on the
+# bench graph (234K and 229K pairs/s against 233K) and slower on the held-out
+# 2M-node graph (125.9K and 121.7K against 127.5K) and on edge pairs: the
+# shallower schedules they pick add more walk steps than the vector reads they
+# save.  The shipped checkpoint is labelled with 1.
+RHO_V = 1.0
 
 
 def log(msg):
@@ -63,16 +79,18 @@ def reference(gg, s, t):
     return G.geer_query(gg.handle, s, t, EPS_REF, p, fixed_ell_b=1 << 20)
 
 
-def label(feats, runs, r_ref, rng, n_rho=4):
+def label(feats, runs, r_ref, rng, n_rho=4, rho_v=RHO_V):
     """Labelled samples (X raw, Y, W) with sampled cost ratios."""
     n = feats.shape[0]
     keys = list(runs)
     w2 = (2.0 ** feats[:, 3] - 1.0) + (2.0 ** feats[:, 4] - 1.0)
+    long_row = np.maximum(np.rint(2.0 ** feats[:, 0]), np.rint(2.0 ** feats[:, 1])) > MEMBER_ROW_MAX
     cost_parts = []
     for (lb, tau) in keys:
         _, st = runs[(lb, tau)]
-        steps = 2.0 * st["walk_pairs"] * np.maximum(st["ell"] - st["ell_b"], 0)
         eff = st["ell_b"]
+        reads = (eff >= 2) | ((eff == 1) & long_row)
+        steps = 2.0 * st["walk_pairs"] * np.maximum(st["ell"] - eff, 0) * np.where(reads, rho_v, 1.0)
         cost_parts.append((steps, eff))
     Xs, Ys, Ws = [], [], []
     for _ in range(n_rho):
@@ -97,7 +115,7 @@ def label(feats, runs, r_ref, rng, n_rho=4):
     return np.concatenate(Xs), np.concatenate(Ys), np.concatenate(Ws)
 
 
-def graph_runs(g, nq, n_edge, n_deg, eps_choices, seed, rng, taus=None):
+def graph_runs(g, nq, n_edge, n_deg, eps_choices, seed, rng, taus=None, rho_v=RHO_V):
     """Features, schedule sweep and reference answers on one training graph:
     ``nq`` uniform pairs, ``n_edge`` pairs that are edges of the graph and
     ``n_deg`` pairs with both endpoints drawn by degree.  Each pair draws its
@@ -120,7 +138,7 @@ def graph_runs(g, nq, n_edge, n_deg, eps_choices, seed, rng, taus=None):
         r_ref = reference(gg, s, t)
         log(f"  reference answers (SMM only, eps {EPS_REF})")
         feats = G.geer_features(gg.handle, s, t, eps)
-    return label(feats, runs, r_ref, rng)
+    return label(feats, runs, r_ref, rng, rho_v=rho_v)
 
 
 # Training graphs: (generator, uniform pairs, edge pairs, degree-drawn pairs,
@@ -168,6 +186,8 @@ def main(argv=None):
                          "12,500 uniform pairs at eps 0.05 (200,000 GEER runs)")
     ap.add_argument("--w-tau", type=float, default=None,
                     help="loss weight of the tau output (default: the labelling rule's 0.25)")
+    ap.add_argument("--rho-v", type=float, default=RHO_V,
+                    help="relative cost of a walk step that reads the pair's vector values")
     ap.add_argument("--samples-out", default=None, help="save the labelled samples (.npz)")
     ap.add_argument("--samples-in", default=None,
                     help="train on labelled samples saved by --samples-out instead of sweeping")
@@ -185,7 +205,7 @@ def main(argv=None):
         taus = tuple(int(x) for x in a.taus.split(","))
         for make, nq, n_edge, n_deg, eps_choices, seed in graphs:
             g = make()
-            parts.append(graph_runs(g, nq, n_edge, n_deg, eps_choices, seed, rng, taus))
+            parts.append(graph_runs(g, nq, n_edge, n_deg, eps_choices, seed, rng, taus, a.rho_v))
             runs_total += (nq + n_edge + n_deg) * len(DEPTHS) * len(taus)
         X = np.concatenate([p[0] for p in parts])
         Y = np.concatenate([p[1] for p in parts])
