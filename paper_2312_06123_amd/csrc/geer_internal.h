@@ -169,6 +169,11 @@ struct geer_graph {
     // stream; the events order the two slot sets between them
     hipStream_t stream2 = nullptr;
     hipEvent_t ev_smm[2] = {nullptr, nullptr}, ev_clean[2] = {nullptr, nullptr};
+    // pinned host staging of the per-pair depth read and the batch order
+    // upload; pin_ev follows the last copy that reads it
+    char *h_pin = nullptr;
+    size_t h_pin_bytes = 0;
+    hipEvent_t pin_ev = nullptr;
     int num_cus = 0;
     // CSR on device
     int32_t *d_row_ptr = nullptr;

@@ -435,6 +435,7 @@ geer_status geer_graph_create(int32_t n, const int32_t *row_ptr, const int32_t *
     for (int i = 0; i < 2 && ev_ok; ++i)
         ev_ok = hipEventCreateWithFlags(&g->ev_smm[i], hipEventDisableTiming) == hipSuccess &&
                 hipEventCreateWithFlags(&g->ev_clean[i], hipEventDisableTiming) == hipSuccess;
+    if (ev_ok) ev_ok = hipEventCreateWithFlags(&g->pin_ev, hipEventDisableTiming) == hipSuccess;
     if (!ev_ok) {
         geer_graph_destroy(g);
         return fail(GEER_E_DEVICE, "stream or event creation failed");
@@ -474,6 +475,11 @@ void geer_graph_destroy(geer_graph *g)
         if (g->ev_smm[i]) (void)hipEventDestroy(g->ev_smm[i]);
         if (g->ev_clean[i]) (void)hipEventDestroy(g->ev_clean[i]);
     }
+    if (g->pin_ev) {
+        (void)hipEventSynchronize(g->pin_ev);
+        (void)hipEventDestroy(g->pin_ev);
+    }
+    if (g->h_pin) (void)hipHostFree(g->h_pin);
     if (g->stream2) (void)hipStreamDestroy(g->stream2);
     if (g->stream) (void)hipStreamDestroy(g->stream);
     delete g;

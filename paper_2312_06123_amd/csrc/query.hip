@@ -493,6 +493,23 @@ struct GraphSig {
 
 // The whole query pipeline on device-resident inputs (already in qstate).
 // h_s / h_t: host copies of the pairs (used for planning only).
+// Pinned host staging of at least `bytes` (grown as needed).  Waits for the
+// last copy that read it, so the host may overwrite it.
+static geer_status pinned_staging(geer_graph *g, size_t bytes, char **out)
+{
+    GEER_HIP(hipEventSynchronize(g->pin_ev));
+    if (bytes > g->h_pin_bytes) {
+        if (g->h_pin) GEER_HIP(hipHostFree(g->h_pin));
+        g->h_pin = nullptr;
+        g->h_pin_bytes = 0;
+        const size_t cap = bytes + bytes / 4 + 4096;
+        GEER_HIP(hipHostMalloc((void **)&g->h_pin, cap, hipHostMallocDefault));
+        g->h_pin_bytes = cap;
+    }
+    *out = g->h_pin;
+    return GEER_OK;
+}
+
 static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
                                const int32_t *d_fixed, double min_eps, const int32_t *h_s,
                                const int32_t *h_t)
@@ -530,17 +547,21 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
         // depths are known: bucket pairs of equal SMM depth into the same
         // batches so that dense hops run on full batches, shallowest first
         // (the first group needs hop 1 only, so walks start at once)
-        std::vector<int32_t> ellh(c.nq), act(c.nq), fb(c.nq);
-        if (graph_mode)
-            GEER_HIP(hipMemcpyAsync(taus.data(), c.qs.tau_q, c.nq * sizeof(int32_t), hipMemcpyDeviceToHost,
-                                    c.stream));
-        GEER_HIP(hipMemcpyAsync(target.data(), c.qs.lb_target, c.nq * sizeof(int32_t),
-                                hipMemcpyDeviceToHost, c.stream));
-        GEER_HIP(hipMemcpyAsync(ellh.data(), c.qs.ell, c.nq * sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
-        GEER_HIP(hipMemcpyAsync(act.data(), c.qs.active_smm, c.nq * sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
-        GEER_HIP(hipMemcpyAsync(fb.data(), c.qs.fallback, c.nq * sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+        // one copy of the per-pair int32 arrays from ell to tau_q (they are
+        // consecutive in the query state) into pinned host memory
+        const int32_t *base = c.qs.ell;
+        const size_t span = (size_t)(c.qs.tau_q - base) + (size_t)c.nq;
+        char *pin = nullptr;
+        GEER_TRY(pinned_staging(g, span * sizeof(int32_t), &pin));
+        GEER_HIP(hipMemcpyAsync(pin, base, span * sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
         GEER_HIP(hipStreamSynchronize(c.stream));
-        for (int64_t i = 0; i < c.nq; ++i) target[i] = act[i] ? std::min(target[i], ellh[i]) : 0;
+        const int32_t *h = reinterpret_cast<const int32_t *>(pin);
+        auto host = [&](const int32_t *dev) { return h + (dev - base); };
+        const int32_t *tgt = host(c.qs.lb_target), *ellh = host(c.qs.ell), *act = host(c.qs.active_smm);
+        const int32_t *fbh = host(c.qs.fallback), *tq = host(c.qs.tau_q);
+        std::vector<int32_t> fb(fbh, fbh + c.nq);
+        for (int64_t i = 0; i < c.nq; ++i) target[i] = act[i] ? std::min(tgt[i], ellh[i]) : 0;
+        if (graph_mode) std::copy(tq, tq + c.nq, taus.begin());
         std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
             if (fb[a] != fb[b]) return fb[a] < fb[b];  // fallback pairs last
             return target[a] < target[b];
@@ -548,7 +569,16 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
         n_static = 0;
         while (n_static < c.nq && !fb[ord[n_static]]) ++n_static;
     }
-    GEER_HIP(hipMemcpyAsync(c.qs.ord, ord.data(), c.nq * sizeof(int32_t), hipMemcpyHostToDevice, c.stream));
+    if (p.schedule != GEER_SCHEDULE_GREEDY) {
+        // the staging buffer was read above (after its last upload completed)
+        char *pin = nullptr;
+        GEER_TRY(pinned_staging(g, (size_t)c.nq * sizeof(int32_t), &pin));
+        std::memcpy(pin, ord.data(), (size_t)c.nq * sizeof(int32_t));
+        GEER_HIP(hipMemcpyAsync(c.qs.ord, pin, c.nq * sizeof(int32_t), hipMemcpyHostToDevice, c.stream));
+        GEER_HIP(hipEventRecord(g->pin_ev, c.stream));
+    } else {
+        GEER_HIP(hipMemcpyAsync(c.qs.ord, ord.data(), c.nq * sizeof(int32_t), hipMemcpyHostToDevice, c.stream));
+    }
     // groups in order: the static phase (known depths), then the greedy one
     struct Job {
         GroupPlan gp;
