@@ -322,6 +322,40 @@ def test_geer_deterministic_and_device_entry(cl_graph):
         assert np.array_equal(dr.cpu().numpy(), r1)
 
 
+def test_geer_calls_on_alternating_streams_identical(cl_graph):
+    # FIXED depths: each call reads the pairs' depths through the handle's
+    # pinned staging buffer and uploads the batch order from it; calls queued
+    # back to back on two streams (no host wait between them) must not see
+    # each other's staging
+    import torch
+
+    g, lam = cl_graph
+    s, t = I.uniform_pairs(g.n, 400, 16)
+    depth = np.random.default_rng(16).integers(0, 4, len(s)).astype(np.int32)
+    depth2 = depth[::-1].copy()
+    with _graph(g, lam) as gg:
+        ref = [G.geer_query(gg.handle, s, t, 0.1, G.geer_params_default(seed=31), fixed_ell_b=d)
+               for d in (depth, depth2)]
+        ds = torch.from_numpy(s).cuda()
+        dt = torch.from_numpy(t).cuda()
+        de = torch.full((len(s),), 0.1, dtype=torch.float64, device="cuda")
+        streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+        outs = []
+        for k in range(6):
+            d = (depth, depth2)[k % 2]
+            dr = torch.full((len(s),), float("nan"), dtype=torch.float64, device="cuda")
+            st = streams[k % 2]
+            st.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(st):
+                p = G.geer_params_default(seed=31, schedule=G.GEER_SCHEDULE_FIXED, fixed_ell_b=d.ctypes.data,
+                                          stream=st.cuda_stream)
+                G.geer_query_device(gg.handle, ds, dt, de, dr, p)
+            outs.append((k, dr))
+        torch.cuda.synchronize()
+        for k, dr in outs:
+            assert np.array_equal(dr.cpu().numpy(), ref[k % 2]), k
+
+
 def test_geer_slot_reuse_and_repeat_calls_identical(cl_graph):
     # groups of 1 or 3 batches reuse the same vector slots many times within
     # a call; results and schedules must equal a call where nothing is reused
