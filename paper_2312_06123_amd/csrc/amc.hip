@@ -194,7 +194,8 @@ __global__ __launch_bounds__(256) void k_walk(QState qs, int64_t q0, int nq, int
                                               const void *__restrict__ rec, uint32_t rec_sb,
                                               uint32_t rec_sd, const T *__restrict__ pool,
                                               uint32_t key0, uint32_t key1, int64_t qid_offset,
-                                              double2 *__restrict__ zpart, int part, int nparts)
+                                              double2 *__restrict__ zpart, int part, int nparts,
+                                              const unsigned long long *__restrict__ filter)
 {
     using T2 = typename Val2<T>::type;
     // chunk offsets in LDS as 32-bit values when they fit
@@ -241,6 +242,9 @@ __global__ __launch_bounds__(256) void k_walk(QState qs, int64_t q0, int nq, int
         // one-hop vectors: s*(u) = 1/d(u) on N(s), t*(u) = 1/d(u) on N(t)
         // (the values the hop-1 scatter stored), evaluated from the graph
         const bool member = voff >= 0 && one_hop_from_graph(qs.lb[q], ds, dt);
+        // pairs with a walk filter read their values only at nodes it holds
+        const unsigned long long *fq =
+            filter && walk_filtered(voff, qs.lb[q], ds, dt) ? filter + (size_t)lo * kWalkFilterWords : nullptr;
         if (member) {
             // the wave's previous reads of s_rows have completed (their values
             // were consumed), so the rows can be overwritten in place
@@ -275,6 +279,9 @@ __global__ __launch_bounds__(256) void k_walk(QState qs, int64_t q0, int nq, int
                     const double inv = (double)(T)(1.0 / (double)d);
                     xv = lds_row_contains(s_rows[wv][0], u) ? inv : 0.0;
                     yv = lds_row_contains(s_rows[wv][1], u) ? inv : 0.0;
+                } else if (fq && (fq[walk_filter_word(u)] & walk_filter_mask(u)) != walk_filter_mask(u)) {
+                    xv = 0.0;  // u is in neither support
+                    yv = 0.0;
                 } else {
                     T2 w = *reinterpret_cast<const T2 *>(pool + voff + (size_t)u * VS);
                     xv = (double)w.x;
@@ -294,6 +301,53 @@ __global__ __launch_bounds__(256) void k_walk(QState qs, int64_t q0, int nq, int
         }
         if (lane == 0) zpart[c] = make_double2(zs, z2);
     }
+}
+
+// ----------------------------------------------------------------------------
+// walk filters (one block per group position)
+// ----------------------------------------------------------------------------
+
+// Inserts supp(x) U supp(y) of each filtered pair that still walks: N(s) and
+// N(t) at depth 1, the nodes two hops from s or t at depth 2 (every node a
+// hop-2 vector can be nonzero on).  Built in LDS, then written out whole.
+__global__ __launch_bounds__(256) void k_walk_filter(QState qs, int64_t q0, const int32_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ col_idx,
+                                                     unsigned long long *__restrict__ filter)
+{
+    __shared__ unsigned long long f[kWalkFilterWords];
+    const int64_t q = qs.ord[q0 + blockIdx.x];
+    const int32_t s = qs.s[q], t = qs.t[q], lb = qs.lb[q];
+    const int32_t bs = row_ptr[s], ds = row_ptr[s + 1] - bs;
+    const int32_t bt = row_ptr[t], dt = row_ptr[t + 1] - bt;
+    if (!qs.active_amc[q] || !walk_filtered(qs.vec_off[q], lb, ds, dt)) return;
+    for (int w = threadIdx.x; w < kWalkFilterWords; w += blockDim.x) f[w] = 0ull;
+    __syncthreads();
+    auto insert = [&](int32_t v) { atomicOr(&f[walk_filter_word(v)], walk_filter_mask(v)); };
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+    for (int side = 0; side < 2; ++side) {
+        const int32_t b = side ? bt : bs, d = side ? dt : ds;
+        if (lb == 1) {
+            for (int k = threadIdx.x; k < d; k += blockDim.x) insert(col_idx[b + k]);
+        } else {
+            for (int k = wave; k < d; k += waves) {
+                const int32_t v = col_idx[b + k];
+                const int32_t bv = row_ptr[v], dv = row_ptr[v + 1] - bv;
+                for (int m = lane; m < dv; m += 64) insert(col_idx[bv + m]);
+            }
+        }
+    }
+    __syncthreads();
+    unsigned long long *out = filter + (size_t)blockIdx.x * kWalkFilterWords;
+    for (int w = threadIdx.x; w < kWalkFilterWords; w += blockDim.x) out[w] = f[w];
+}
+
+geer_status launch_walk_filter(geer_graph *g, const QueryCtx &c, int64_t q0, int nq, unsigned long long *filter,
+                               hipStream_t st)
+{
+    if (nq <= 0) return GEER_OK;
+    hipLaunchKernelGGL(k_walk_filter, dim3(nq), dim3(256), 0, st, c.qs, q0, g->d_row_ptr, g->d_col_idx, filter);
+    GEER_HIP(hipGetLastError());
+    return GEER_OK;
 }
 
 // ----------------------------------------------------------------------------
@@ -402,6 +456,7 @@ geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hip
     const void *rec = g->d_walk_rec;
     const uint32_t sb = (uint32_t)g->rec_sb, sd = (uint32_t)g->rec_sd;
     auto *zp = ext ? ext->zpart : ws.zpart.as<double2>();
+    const unsigned long long *filt = grp.vstride == kCols ? grp.filter : nullptr;
     for (int round = 0; round < rounds; ++round) {
         // walk steps of the batch (all, and those reading SMM vectors) for the
         // profiler's byte count, else into scratch
@@ -416,7 +471,7 @@ geer_status amc_phase(geer_graph *g, const QueryCtx &c, const AmcGroup &grp, hip
 #define GEER_WALK_LAUNCH(T, RB, VS)                                                                 \
     hipLaunchKernelGGL((k_walk<T, RB, VS>), dim3(blocks), dim3(256), 0, st, c.qs, grp.q0, nq, round, \
                        chunk_off, d_total, g->d_row_ptr, g->d_col_idx, rec, sb, sd,                 \
-                       (const T *)grp.pool, key0, key1, c.qid_offset, zp, part, kWalkParts)
+                       (const T *)grp.pool, key0, key1, c.qid_offset, zp, part, kWalkParts, filt)
 #define GEER_WALK_LAUNCH_T(T, VS)                       \
     do {                                                \
         if (g->walk_rec_bytes == 8) GEER_WALK_LAUNCH(T, 8, VS); \

@@ -101,6 +101,7 @@ struct Workspace {
     DevBuf acc;       // sparse hop 2: per slot n x kCols fixed-point accumulators (kept all zero)
     DevBuf meta;      // per-slot masks (active, hop-2 cleanup, hop-2 paths, static levels)
     DevBuf feat;      // learned scheduler: per-pair features
+    DevBuf wfilter;   // walk filters: per slot set, per group position
     int acc_slots = 0;          // slots of all-zero accumulators held in acc
     bool in_use = false;        // a call holds entries in the slot buffers (set until it restores them)
     std::vector<char> a_dirty;  // per slot: buffer A was written by a dense hop
@@ -316,6 +317,27 @@ __host__ __device__ inline double bernstein_of(double nz, double var, double psi
 // sorted row of s gives the same value as the random read of the buffer.
 constexpr int32_t kMemberRowMax = 256;
 
+// Walk filters: a blocked Bloom filter (2048 words of 64 bits, two bits per
+// node in one word) of supp(x) U supp(y) for each pair that walks over
+// vectors read from the batch slots with a support small enough to filter:
+// depth 2, or depth 1 with a row of s or t longer than kMemberRowMax.  A walk
+// step whose node is not in the filter reads no vector values (both are
+// exactly zero off the supports); a Bloom filter has no false negatives.
+constexpr int kWalkFilterWords = 2048;
+__host__ __device__ __forceinline__ bool walk_filtered(int64_t voff, int32_t lb, int32_t ds, int32_t dt)
+{
+    return voff >= 0 && (lb == 2 || (lb == 1 && (ds > kMemberRowMax || dt > kMemberRowMax)));
+}
+__device__ __forceinline__ uint32_t walk_filter_word(int32_t v)
+{
+    return ((uint32_t)v * 0x9E3779B1u) >> 21;
+}
+__device__ __forceinline__ unsigned long long walk_filter_mask(int32_t v)
+{
+    const uint32_t h = (uint32_t)v * 0x85EBCA77u;
+    return (1ull << (h >> 26)) | (1ull << ((h >> 20) & 63u));
+}
+
 // blocks per column of the global sparse hop 2: at least kPushSplit, up to
 // kPushSplitMax when few columns take that path (hub columns)
 constexpr int kPushSplit = 8;
@@ -417,6 +439,9 @@ geer_status launch_hop2_sparse(geer_graph *g, const QueryCtx &c, const SlotArgs 
 // blocks per column for a global hop-2 pass over `ncols` columns
 int hop2_split(int ncols);
 geer_status launch_zero(geer_graph *g, void *p, size_t bytes, hipStream_t st);
+// walk filters of group positions [0, nq) from q0 (after the group's SMM)
+geer_status launch_walk_filter(geer_graph *g, const QueryCtx &c, int64_t q0, int nq,
+                               unsigned long long *filter, hipStream_t st);
 // make at least min(want, what fits) slots of hop-2 accumulators available;
 // returns the slot count (0 with *err set on failure)
 int ensure_hop2_acc(geer_graph *g, int want, hipStream_t st, geer_status *err);
@@ -446,6 +471,8 @@ struct AmcGroup {
     int rounds = 0;
     int64_t zpart_cap = 0;
     int64_t *sticky = nullptr;
+    // per group position: walk filter (kWalkFilterWords words; nullptr: none)
+    const unsigned long long *filter = nullptr;
 };
 
 // AMC buffers supplied by the caller instead of the workspace (nothing is

@@ -27,7 +27,8 @@ std::vector<DevBuf *> workspace_bufs(geer_graph *g)
 {
     Workspace &w = g->ws;
     return {&w.pool, &w.bits,   &w.part, &w.segbuf, &w.colstat, &w.qstate, &w.chunk_off,
-            &w.zpart, &w.misc, &w.io,   &w.acc,    &w.meta,    &w.feat,   &w.hpart};
+            &w.zpart, &w.misc, &w.io,   &w.acc,    &w.meta,    &w.feat,   &w.hpart,
+            &w.wfilter};
 }
 
 geer_status DevBuf::reserve(size_t want)

@@ -604,6 +604,15 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
         if (is_static && jobs.size() >= 3) std::rotate(jobs.begin() + 1, jobs.end() - 1, jobs.end());
     }
     for (size_t i = 0; i < jobs.size(); ++i) jobs[i].set = (int)(i % sets);
+    // walk filters: per slot set, room for the largest group
+    int64_t job_nq_max = 0;
+    for (const Job &jb : jobs)
+        job_nq_max = std::max<int64_t>(job_nq_max, std::min<int64_t>(jb.gp.pend, jb.gp.p0 + jb.gp.nbat * B) - jb.gp.p0);
+    GEER_TRY(g->ws.wfilter.reserve((size_t)sets * std::max<int64_t>(job_nq_max, 1) * kWalkFilterWords *
+                                   sizeof(unsigned long long)));
+    auto filter_of = [&](int set) {
+        return g->ws.wfilter.as<unsigned long long>() + (size_t)set * job_nq_max * kWalkFilterWords;
+    };
     const size_t set_vals = (size_t)G * 3 * g->n * kCols, set_words = (size_t)G * 3 * g->n * kBitWords;
     auto view = [&](int set) {
         SlotView v{g->ws.pool.as<char>() + set * set_vals * vs, g->ws.bits.as<uint32_t>() + set * set_words,
@@ -644,6 +653,7 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
         grp.nq = std::min<int64_t>(jb.gp.pend, jb.gp.p0 + jb.gp.nbat * B) - grp.q0;
         grp.pool = view(jb.set).pool;
         grp.value_size = vs;
+        grp.filter = filter_of(jb.set);
         if (fixed) {
             grp.fixed_plan = true;
             grp.rounds = group_rounds(jb);
@@ -669,6 +679,9 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
             if (sB != sA && i >= j0 + 2) GEER_TRY(cleanup(i - 2));
             GEER_TRY(smm_group(g, c, view(jb.set), meta(jb.set), jb.gp, jb.is_static, target.data(), h_s,
                                h_t, ord.data(), col_tile, max_hops, recs[jb.set]));
+            GEER_TRY(launch_walk_filter(g, c, jb.gp.p0,
+                                        (int)(std::min<int64_t>(jb.gp.pend, jb.gp.p0 + jb.gp.nbat * B) - jb.gp.p0),
+                                        filter_of(jb.set), sA));
             if (sB != sA) GEER_HIP(hipEventRecord(g->ev_smm[jb.set], sA));
         }
         if (sB != sA)
@@ -711,7 +724,7 @@ static geer_status run_queries(geer_graph *g, QueryCtx &c, const geer_params &p,
         sig.add(sB);
         const Workspace &w = g->ws;
         for (const DevBuf *b : {&w.pool, &w.bits, &w.part, &w.segbuf, &w.colstat, &w.hpart, &w.qstate,
-                                &w.chunk_off, &w.zpart, &w.misc, &w.acc, &w.meta})
+                                &w.chunk_off, &w.zpart, &w.misc, &w.acc, &w.meta, &w.wfilter})
             sig.add(b->ptr);
         sig.add(w.acc_slots);
         sig.add(w.nq_cap);
