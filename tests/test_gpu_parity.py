@@ -322,6 +322,31 @@ def test_geer_deterministic_and_device_entry(cl_graph):
         assert np.array_equal(dr.cpu().numpy(), r1)
 
 
+def test_geer_walk_filters_exact(cl_graph):
+    # Walks of depth-2 pairs, and of depth-1 pairs with a row longer than 256,
+    # read their vector values only at nodes in a per-pair hash filter of the
+    # supports.  FP64 vectors, every pair must agree with the checker: uniform
+    # pairs (small supports, most steps skip the read), degree-drawn pairs
+    # (hub endpoints: supports over much of the graph, many filter
+    # collisions) and depth-1 pairs of hubs
+    g, lam = cl_graph
+    deg = g.degrees()
+    su, tu = I.uniform_pairs(g.n, 120, 17)
+    sd, td = I.degree_pairs(g, 120, 18)
+    s, t = np.concatenate([su, sd]), np.concatenate([tu, td])
+    depth = np.full(len(s), 2, dtype=np.int32)
+    hub = np.flatnonzero((deg[s] > 256) | (deg[t] > 256))
+    depth[hub[: len(hub) // 2]] = 1
+    assert (depth == 1).sum() >= 4
+    with _graph(g, lam) as gg:
+        p = G.geer_params_default(seed=19, flags=G.GEER_FLAG_FP64_VECTORS)
+        r, st = G.geer_query(gg.handle, s, t, 0.05, p, stats=True, fixed_ell_b=depth)
+    ro, sto = oracle.geer(g.row_ptr, g.col_idx, s, t, 0.05, lam, seed=19, schedule="fixed", fixed_lb=depth)
+    cnt = parity.compare(g, s, t, 0.05, lam, st, sto, tau=5, seed=19, fp64=True, label="walk filters fp64")
+    assert cnt["agree"] == len(s)
+    assert np.all(np.abs(r - ro) <= 1e-12 * np.maximum(1.0, np.abs(ro)))
+
+
 def test_geer_calls_on_alternating_streams_identical(cl_graph):
     # FIXED depths: each call reads the pairs' depths through the handle's
     # pinned staging buffer and uploads the batch order from it; calls queued
