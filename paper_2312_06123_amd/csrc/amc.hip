@@ -8,6 +8,8 @@
 // stride over all chunks of all queries of a group in one launch.  Each chunk
 // writes (sum Z, sum Z^2) to its own slot and the stop kernel adds the slots
 // of a query in a fixed order: results do not depend on scheduling.
+#include <type_traits>
+
 #include "geer_internal.h"
 
 namespace geer {
@@ -149,20 +151,27 @@ __global__ __launch_bounds__(1024) void k_amc_bound(QState qs, int64_t q0, int n
 // degree fit 64 bits, else 16-byte {v, b, d, -}.
 template <int RB> struct WalkRec;
 template <> struct WalkRec<8> {
-    static __device__ __forceinline__ void load(const void *rec, int64_t e, uint32_t sb,
-                                                uint32_t sd, int32_t &v, int32_t &b, int32_t &d)
+    using Raw = uint64_t;
+    static __device__ __forceinline__ Raw fetch(const void *rec, int64_t e)
     {
-        const uint64_t x = __builtin_nontemporal_load(static_cast<const uint64_t *>(rec) + e);
+        return __builtin_nontemporal_load(static_cast<const uint64_t *>(rec) + e);
+    }
+    static __device__ __forceinline__ void decode(Raw x, uint32_t sb, uint32_t sd, int32_t &v, int32_t &b,
+                                                  int32_t &d)
+    {
         v = (int32_t)(x & ((1ull << sb) - 1));
         b = (int32_t)((x >> sb) & ((1ull << (sd - sb)) - 1));
         d = (int32_t)(x >> sd);
     }
 };
 template <> struct WalkRec<16> {
-    static __device__ __forceinline__ void load(const void *rec, int64_t e, uint32_t, uint32_t,
-                                                int32_t &v, int32_t &b, int32_t &d)
+    using Raw = int4;
+    static __device__ __forceinline__ Raw fetch(const void *rec, int64_t e)
     {
-        const int4 x = static_cast<const int4 *>(rec)[e];
+        return static_cast<const int4 *>(rec)[e];
+    }
+    static __device__ __forceinline__ void decode(Raw x, uint32_t, uint32_t, int32_t &v, int32_t &b, int32_t &d)
+    {
         v = x.x;
         b = x.y;
         d = x.z;
@@ -259,37 +268,74 @@ __global__ __launch_bounds__(256) void k_walk(QState qs, int64_t q0, int nq, int
         const uint32_t qid = (uint32_t)(q + qid_offset);
         const uint32_t c2 = ((uint32_t)round << 1) | side;
         double acc = 0.0;
-        if (valid) {
-            int32_t u = side ? t : s;
+        if (valid && lf > 0) {
             int32_t b = side ? bt : bs, d = side ? dt : ds;
-            uint4 r4 = make_uint4(0, 0, 0, 0);
-            for (int32_t step = 0; step < lf; ++step) {
-                if ((step & 3) == 0)
-                    r4 = philox4x32_10(make_uint4((uint32_t)step >> 2, (uint32_t)k, c2, qid),
-                                       key0, key1);
-                // the next node is row u's (draw mod d(u))-th entry; its record
-                // also carries that node's row start and degree
-                const int64_t e = b + (int32_t)(pick_word(r4, (uint32_t)step & 3u) % (uint32_t)d);
-                WalkRec<RB>::load(rec, e, rec_sb, rec_sd, u, b, d);
-                double xv, yv;
-                if (voff < 0) {
-                    xv = u == s ? 1.0 : 0.0;
-                    yv = u == t ? 1.0 : 0.0;
-                } else if (member) {
-                    const double inv = (double)(T)(1.0 / (double)d);
-                    xv = lds_row_contains(s_rows[wv][0], u) ? inv : 0.0;
-                    yv = lds_row_contains(s_rows[wv][1], u) ? inv : 0.0;
-                } else if (fq && (fq[walk_filter_word(u)] & walk_filter_mask(u)) != walk_filter_mask(u)) {
-                    xv = 0.0;  // u is in neither support
-                    yv = 0.0;
-                } else {
-                    T2 w = *reinterpret_cast<const T2 *>(pool + voff + (size_t)u * VS);
-                    xv = (double)w.x;
-                    yv = (double)w.y;
+            uint4 r4 = philox4x32_10(make_uint4(0u, (uint32_t)k, c2, qid), key0, key1);
+            // One loop per kind of pair (wave-uniform), so that no load sits
+            // behind a branch.  The node after a step is row u's (draw mod
+            // d(u))-th entry; its record also carries that node's row start and
+            // degree.  The record of step + 1 is requested after this step's
+            // filter word or values and before they are used: loads complete
+            // in order, so they can be consumed while the record is in flight.
+            // kind 0: indicator vectors, 1: one-hop vectors from LDS rows,
+            // 2: slot values behind a walk filter, 3: slot values.
+            auto walk = [&](auto kind) {
+                constexpr int K = decltype(kind)::value;
+                auto early = [&](int32_t u, unsigned long long &fw, T2 &pv) {
+                    if constexpr (K == 2) fw = fq[walk_filter_word(u)];
+                    if constexpr (K == 3) pv = *reinterpret_cast<const T2 *>(pool + voff + (size_t)u * VS);
+                };
+                auto add = [&](int32_t u, int32_t du, unsigned long long fw, T2 pv) {
+                    double xv, yv;
+                    if constexpr (K == 0) {
+                        xv = u == s ? 1.0 : 0.0;
+                        yv = u == t ? 1.0 : 0.0;
+                    } else if constexpr (K == 1) {
+                        const double inv = (double)(T)(1.0 / (double)du);
+                        xv = lds_row_contains(s_rows[wv][0], u) ? inv : 0.0;
+                        yv = lds_row_contains(s_rows[wv][1], u) ? inv : 0.0;
+                    } else if constexpr (K == 2) {
+                        if ((fw & walk_filter_mask(u)) != walk_filter_mask(u)) {
+                            xv = 0.0;  // u is in neither support
+                            yv = 0.0;
+                        } else {
+                            const T2 w = *reinterpret_cast<const T2 *>(pool + voff + (size_t)u * VS);
+                            xv = (double)w.x;
+                            yv = (double)w.y;
+                        }
+                    } else {
+                        xv = (double)pv.x;
+                        yv = (double)pv.y;
+                    }
+                    // Z_k: S_k adds s(u)/d(s) - t(u)/d(t); T_k adds t(u)/d(t) - s(u)/d(s)
+                    acc += side ? (yv * idt - xv * ids) : (xv * ids - yv * idt);
+                };
+                typename WalkRec<RB>::Raw raw =
+                    WalkRec<RB>::fetch(rec, b + (int32_t)(pick_word(r4, 0u) % (uint32_t)d));
+                int32_t u;
+                for (int32_t step = 0; step + 1 < lf; ++step) {
+                    WalkRec<RB>::decode(raw, rec_sb, rec_sd, u, b, d);
+                    unsigned long long fw = 0ull;
+                    T2 pv{};
+                    early(u, fw, pv);
+                    __builtin_amdgcn_sched_barrier(0);
+                    const uint32_t ns = (uint32_t)step + 1u;
+                    if ((ns & 3u) == 0)
+                        r4 = philox4x32_10(make_uint4(ns >> 2, (uint32_t)k, c2, qid), key0, key1);
+                    raw = WalkRec<RB>::fetch(rec, b + (int32_t)(pick_word(r4, ns & 3u) % (uint32_t)d));
+                    __builtin_amdgcn_sched_barrier(0);
+                    add(u, d, fw, pv);
                 }
-                // Z_k: S_k adds s(u)/d(s) - t(u)/d(t); T_k adds t(u)/d(t) - s(u)/d(s)
-                acc += side ? (yv * idt - xv * ids) : (xv * ids - yv * idt);
-            }
+                WalkRec<RB>::decode(raw, rec_sb, rec_sd, u, b, d);
+                unsigned long long fw = 0ull;
+                T2 pv{};
+                early(u, fw, pv);
+                add(u, d, fw, pv);
+            };
+            if (voff < 0) walk(std::integral_constant<int, 0>{});
+            else if (member) walk(std::integral_constant<int, 1>{});
+            else if (fq) walk(std::integral_constant<int, 2>{});
+            else walk(std::integral_constant<int, 3>{});
         }
         const double z = acc + __shfl_xor(acc, 1);
         double zs = (valid && side == 0) ? z : 0.0;
