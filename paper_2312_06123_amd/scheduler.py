@@ -176,7 +176,7 @@ def train_model(X, Y, W, steps=30000, seed=11, lr=2e-3):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
-    ap.add_argument("--scale", type=float, default=2.0, help="multiplies every graph's pair count")
+    ap.add_argument("--scale", type=float, default=4.0, help="multiplies every graph's pair count")
     ap.add_argument("--steps", type=int, default=60000)
     ap.add_argument("--report", default=None)
     ap.add_argument("--taus", default=",".join(str(x) for x in TAUS),
