@@ -8,6 +8,13 @@
 // stride over all chunks of all queries of a group in one launch.  Each chunk
 // writes (sum Z, sum Z^2) to its own slot and the stop kernel adds the slots
 // of a query in a fixed order: results do not depend on scheduling.
+//
+// A walk step costs one random line fill for its walk record.  The pair's
+// vector values at the new node come from LDS rows (one-hop vectors of short
+// rows), from the node itself (indicator vectors), or from the batch slots,
+// read only when the pair's support filter admits the node (off the supports
+// the values are exact zeros).  Each step requests the next step's record
+// before it consumes its own values, so the two are in flight together.
 #include <type_traits>
 
 #include "geer_internal.h"
